@@ -1,0 +1,131 @@
+"""Seeded synthetic shell-quartet workloads.
+
+This module only draws inputs: shell centres, primitive exponents, contraction
+coefficients and contraction lengths, plus the unit normalisation of each
+contracted shell.  It contains none of the integral method's arithmetic and is
+the one piece shared by the CPU oracle tests and the HIP path.
+
+Layouts (host numpy arrays, the same on the device):
+    centers  float64 [nq][4][3]      Bohr, shells a, b, c, d of each quartet
+    exps     float64 [nq][4][kmax]   primitive exponents (> 0)
+    coefs    float64 [nq][4][kmax]   coefficients multiplying UNnormalised
+                                     primitives x^ax y^ay z^az exp(-z r^2)
+    nprim    int32   [nq][4]         contraction length of each shell, 1..kmax
+
+Entries p >= nprim of exps/coefs are drawn like the others and never read.
+
+Recipe (draw order is fixed so a seed reproduces a workload exactly):
+  1. contraction length per shell (only when it varies),
+  2. centres uniform in [0, box)^3,
+  3. exponents log-uniform in [lo, hi],
+  4. contraction coefficients uniform in [0.1, 1] (1 for K = 1),
+  5. unit normalisation of the contracted shell's x^l component.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def ncart(l: int) -> int:
+    return (l + 1) * (l + 2) // 2
+
+
+def _dfact(n: int) -> float:
+    """(n)!! with (-1)!! = 1."""
+    r = 1.0
+    while n > 1:
+        r *= n
+        n -= 2
+    return r
+
+
+def normalize_shell(l: int, exps: np.ndarray, raw: np.ndarray) -> np.ndarray:
+    """Coefficients of unnormalised primitives giving a contracted shell whose
+    x^l component has unit self-overlap.
+
+    Each primitive is first normalised, N(z,l)^2 = (4z)^l (2z/pi)^{3/2} / (2l-1)!!,
+    then the contraction is scaled by (sum_ij c_i c_j S_ij)^{-1/2} with
+    S_ij = (2l-1)!! / (2(z_i+z_j))^l (pi/(z_i+z_j))^{3/2}, the overlap of the
+    unnormalised x^l primitives.  Works on the trailing axis.
+    """
+    exps = np.asarray(exps, dtype=np.float64)
+    raw = np.asarray(raw, dtype=np.float64)
+    df = _dfact(2 * l - 1)
+    nrm = np.sqrt((4.0 * exps) ** l * (2.0 * exps / np.pi) ** 1.5 / df)
+    c = raw * nrm
+    zs = exps[..., :, None] + exps[..., None, :]
+    S = df / (2.0 * zs) ** l * (np.pi / zs) ** 1.5
+    tot = np.einsum("...i,...ij,...j->...", c, S, c)
+    return c / np.sqrt(tot)[..., None]
+
+
+@dataclass
+class Batch:
+    ls: tuple            # (la, lb, lc, ld) for single-class batches, else None
+    centers: np.ndarray
+    exps: np.ndarray
+    coefs: np.ndarray
+    nprim: np.ndarray
+    lq: np.ndarray | None = None   # int32 [nq][4] for mixed-class batches
+
+    @property
+    def nq(self) -> int:
+        return self.centers.shape[0]
+
+    @property
+    def kmax(self) -> int:
+        return self.exps.shape[2]
+
+
+def class_batch(ls, nq: int, K, seed: int, exp_range=(0.05, 50.0), box: float = 8.0,
+                kmax: int | None = None) -> Batch:
+    """One class (la lb|lc ld), nq quartets.
+
+    K is an int (same contraction length for every shell) or a pair (lo, hi)
+    for a per-shell length drawn uniformly from lo..hi.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if isinstance(K, (tuple, list)):
+        klo, khi = int(K[0]), int(K[1])
+        nprim = rng.integers(klo, khi + 1, size=(nq, 4)).astype(np.int32)
+        km = khi
+    else:
+        km = int(K)
+        nprim = np.full((nq, 4), km, dtype=np.int32)
+    if kmax is None:
+        kmax = km
+    centers = rng.uniform(0.0, box, size=(nq, 4, 3))
+    lo, hi = exp_range
+    exps = np.exp(rng.uniform(np.log(lo), np.log(hi), size=(nq, 4, kmax)))
+    if km == 1 and not isinstance(K, (tuple, list)):
+        raw = np.ones((nq, 4, kmax))
+    else:
+        raw = rng.uniform(0.1, 1.0, size=(nq, 4, kmax))
+    coefs = np.zeros((nq, 4, kmax))
+    for q in range(nq):
+        for s in range(4):
+            k = int(nprim[q, s])
+            coefs[q, s, :k] = normalize_shell(int(ls[s]), exps[q, s, :k], raw[q, s, :k])
+            coefs[q, s, k:] = raw[q, s, k:]
+    return Batch(tuple(int(x) for x in ls), centers, exps, coefs, nprim)
+
+
+def subset(b: Batch, idx) -> Batch:
+    idx = np.asarray(idx)
+    return Batch(b.ls, b.centers[idx].copy(), b.exps[idx].copy(), b.coefs[idx].copy(),
+                 b.nprim[idx].copy(), None if b.lq is None else b.lq[idx].copy())
+
+
+# Named workloads (sizes of the paper's high angular momentum classes).
+def gggg_k1(nq: int = 64, seed: int = 1001) -> Batch:
+    """(gg|gg), l = 4, uncontracted, exponents log-uniform [0.05, 50]."""
+    return class_batch((4, 4, 4, 4), nq, 1, seed, exp_range=(0.05, 50.0))
+
+
+def iiii(K: int = 1, nq: int = 512, seed: int | None = None) -> Batch:
+    """(ii|ii), l = 6, K primitives per shell, exponents log-uniform [0.05, 200]."""
+    if seed is None:
+        seed = 1002 if K == 1 else 1003
+    return class_batch((6, 6, 6, 6), nq, K, seed, exp_range=(0.05, 200.0))
