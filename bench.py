@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the (ab|cd) hot path on one MI355X.
+
+A step is one eri4_batch call over the whole batch: Boys function, Hermite
+integrals, both Hermite-to-Cartesian MFMA transforms and the output write, for
+512 (ii|ii) quartets (l = 6, Cartesian, 784 x 784 integrals each) with inputs
+already resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload iiii_k1|iiii_k5|gggg_k1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6  # MI355X published dense FP64 (vector and matrix)
+METRIC = "(ii|ii) integrals/s + % FP64 peak; mixed-prec vs FP64 speedup at ≤1e-10 err"
+KERNEL = "eri4_fused_kernel"
+SOURCES = ["paper_2307_03452_amd/csrc/eri4.hip", "paper_2307_03452_amd/csrc/eri4_internal.h",
+           "paper_2307_03452_amd/csrc/eri4_tables.cpp"]
+
+WORKLOADS = {
+    "iiii_k1": dict(ls=(6, 6, 6, 6), K=1, nq=512, seed=1002, exps=(0.05, 200.0),
+                    desc="(ii|ii) l=6 Cartesian, K=1 per shell, 512 quartets, exponents log-uniform [0.05,200], "
+                         "centres uniform in an 8-Bohr cube, unit-normalised shells, FP64 out [512][28][28][28][28]"),
+    "iiii_k5": dict(ls=(6, 6, 6, 6), K=5, nq=512, seed=1003, exps=(0.05, 200.0),
+                    desc="(ii|ii) l=6 Cartesian, K=5 per shell (K_bra=K_ket=25), coefficients U[0.1,1], 512 quartets, "
+                         "exponents log-uniform [0.05,200], 8-Bohr cube, FP64 out"),
+    "gggg_k1": dict(ls=(4, 4, 4, 4), K=1, nq=64, seed=1001, exps=(0.05, 50.0),
+                    desc="(gg|gg) l=4 Cartesian, K=1, 64 quartets, exponents log-uniform [0.05,50], 8-Bohr cube"),
+}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for s in SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def make_batch(wl):
+    from paper_2307_03452_amd import inputs
+    return inputs.class_batch(wl["ls"], wl["nq"], wl["K"], seed=wl["seed"], exp_range=wl["exps"])
+
+
+def time_gpu(wl, b, steps, warmup):
+    import torch
+    from paper_2307_03452_amd import eri4, metrics
+    d = lambda a: torch.from_numpy(a).cuda()
+    C, E, Co, N = d(b.centers), d(b.exps), d(b.coefs), d(b.nprim)
+    ls = wl["ls"]
+    out = torch.empty((b.nq,) + tuple(metrics.ncart(l) for l in ls), dtype=torch.float64, device="cuda")
+    eri4.init()
+    for _ in range(warmup):
+        eri4.batch(ls, C, E, Co, N, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        eri4.batch(ls, C, E, Co, N, out=out, stream=stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(z) for a, z in ev]
+    return out, wall, launch_ms
+
+
+def parity_sample(wl, b, out, n=2):
+    import numpy as np
+    import oracle
+    from paper_2307_03452_amd import inputs
+    idx = [0, b.nq - 1][:n]
+    s = inputs.subset(b, idx)
+    o = oracle.eri_md4(wl["ls"], s.centers, s.exps, s.coefs, s.nprim)
+    g = out[idx].cpu().numpy()
+    return max(float(np.abs(g[i] - o[i]).max() / np.abs(o[i]).max()) for i in range(len(idx)))
+
+
+def cpu_baseline(wl, b, budget_s=12.0):
+    """The oracle (as it stands) on the host cores, on the first quartets of the
+    same workload, grown in chunks until about budget_s of CPU work."""
+    import oracle
+    from paper_2307_03452_amd import inputs, metrics
+    threads = oracle.max_threads()
+    done, t_tot = 0, 0.0
+    chunk = max(threads, 1)
+    while t_tot < budget_s and done < b.nq:
+        idx = list(range(done, min(b.nq, done + chunk)))
+        s = inputs.subset(b, idx)
+        t0 = time.perf_counter()
+        oracle.eri_md4(wl["ls"], s.centers, s.exps, s.coefs, s.nprim, nthreads=threads)
+        t_tot += time.perf_counter() - t0
+        done += len(idx)
+        if t_tot < budget_s / 8:
+            chunk *= 2
+    ints = done * metrics.integrals_per_quartet(*wl["ls"])
+    return {"value": ints / t_tot, "unit": "integrals/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} of the {b.nq} quartets of the same workload, OpenMP over quartets, "
+                      f"{t_tot:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="iiii_k1", choices=sorted(WORKLOADS))
+    ap.add_argument("--secondary-steps", type=int, default=1,
+                    help="timed steps of the contracted (ii|ii) K=5 batch reported beside the headline (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (quartets shard across GPUs "
+              "with no communication; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2307_03452_amd import metrics
+    wl = WORKLOADS[args.workload]
+    b = make_batch(wl)
+    ls = wl["ls"]
+    out, wall, launch_ms = time_gpu(wl, b, args.steps, args.warmup)
+    ms_step = wall * 1e3 / args.steps
+    ints = b.nq * metrics.integrals_per_quartet(*ls)
+    kb = wl["K"] * wl["K"]
+    flops = b.nq * metrics.md4_flops(*ls, kb, kb)
+    avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
+    achieved = flops / avg_launch_s / 1e12
+    rec = {
+        "metric": METRIC,
+        "value": ints / (wall / args.steps),
+        "unit": "integrals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "quartets": b.nq, "K_per_shell": wl["K"],
+                   "integrals_per_step": ints, "md4_flops_per_step": flops},
+        "pct_fp64_peak": 100.0 * achieved / FP64_PEAK_TFLOPS,
+        "md4_tflops": achieved,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_from_profiles(args.workload),
+                     "kernel": KERNEL, "avg_launch_ms": avg_launch_s * 1e3,
+                     "algorithmic_unit": "MD4 matrix FLOPs per quartet x quartets per launch"},
+    }
+    rec["parity_max_rel_err"] = parity_sample(wl, b, out)
+    if args.secondary_steps > 0 and args.workload == "iiii_k1":
+        wl5 = WORKLOADS["iiii_k5"]
+        b5 = make_batch(wl5)
+        _, wall5, lm5 = time_gpu(wl5, b5, args.secondary_steps, 1)
+        f5 = b5.nq * metrics.md4_flops(*ls, 25, 25)
+        s5 = sum(lm5) / len(lm5) / 1e3
+        rec["secondary"] = {"workload": wl5["desc"], "value": ints / (wall5 / args.secondary_steps),
+                            "unit": "integrals/s", "ms_per_step": wall5 * 1e3 / args.secondary_steps,
+                            "md4_tflops": f5 / s5 / 1e12, "pct_fp64_peak": 100 * f5 / s5 / 1e12 / FP64_PEAK_TFLOPS}
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(wl, b)
+        rec["cpu_baseline"] = cb
+        rec["gpu_over_cpu"] = rec["value"] / cb["value"]
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,141 @@
+/*
+ * eri4.h -- C ABI of the MI355X (gfx950) library for 4-center 2-electron
+ * Coulomb integrals (ab|cd) over contracted Cartesian Gaussian shells, computed
+ * with the matrix form of the McMurchie-Davidson scheme (Asadchev & Valeev,
+ * arXiv:2307.03452, Sec. 2 and Sec. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Primitive Cartesian Gaussian (Sec. 2, first equation):
+ *       phi_a(r) = x_A^ax y_A^ay z_A^az exp(-z_a |r - A|^2)     (UNnormalised)
+ *   A contracted shell of angular momentum l is sum_p c_p phi_a(r; z_p); the
+ *   coefficients c_p passed here multiply the unnormalised primitives (any
+ *   normalisation is the caller's, folded into c_p).
+ * - Cartesian components of a shell are ordered ax = l..0, then ay = l-ax..0
+ *   (az = l - ax - ay): index = (l-ax)(l-ax+1)/2 + az.
+ * - (ab|cd) = sum over primitives of c_a c_b c_c c_d times the integral of
+ *   phi_a(r) phi_b(r) |r - r'|^-1 phi_c(r') phi_d(r') over r and r'.
+ * - All pointers marked "device" are HIP device (or managed) memory on the
+ *   current device; "host" pointers are host memory.  The caller owns every
+ *   buffer; the library never frees or reallocates caller memory.
+ * - stream is a hipStream_t (0 = the null stream).  Compute calls only enqueue
+ *   work on it and return without synchronising; results are ready once the
+ *   stream is synchronised.  A kernel fault surfaces at that synchronisation.
+ * - Arguments are validated on the host before anything is enqueued; on any
+ *   error nothing is written and eri4_last_error() describes the problem.
+ *   Device-resident values (exponents, coefficients, contraction lengths) are
+ *   not read on the host; a quartet whose contraction lengths are outside
+ *   1..kmax gets NaN in every output element.
+ * - No screening is done: every quartet passed is computed (Sec. 3, the
+ *   library interface paragraph).
+ * - Thread safety: calls may come from several host threads; the one-time
+ *   per-device set-up is serialised internally.
+ */
+#ifndef ERI4_H
+#define ERI4_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ERI4_SUCCESS = 0,
+  ERI4_ERROR_INVALID_ARGUMENT = 1, /* a size, pointer or range is wrong     */
+  ERI4_ERROR_UNSUPPORTED = 2,      /* valid but not implemented (e.g. l > max) */
+  ERI4_ERROR_OUT_OF_MEMORY = 3,    /* device allocation during set-up failed  */
+  ERI4_ERROR_HIP = 4,              /* a HIP runtime call failed               */
+  ERI4_ERROR_INTERNAL = 5
+} eri4_status;
+
+/* Largest angular momentum per shell accepted by eri4_batch. */
+#define ERI4_MAX_L 6
+/* Largest contraction length per shell (kmax) accepted by eri4_batch. */
+#define ERI4_MAX_K 16
+/* Largest Boys order m accepted by eri4_boys (covers L = 4 * 7). */
+#define ERI4_MAX_BOYS_M 28
+
+/* Number of Cartesian components of a shell, (l+1)(l+2)/2; -1 if l < 0. */
+int eri4_ncart(int l);
+
+/* Doubles written per quartet by eri4_batch: ncart(la)ncart(lb)ncart(lc)ncart(ld);
+ * -1 on a negative l. */
+int64_t eri4_quartet_size(int la, int lb, int lc, int ld);
+
+/* Message of the last error on the calling thread ("" if none). The pointer
+ * stays valid until the next call from that thread. */
+const char* eri4_last_error(void);
+
+/* Library version string. */
+const char* eri4_version(void);
+
+/* Optional explicit set-up of the current device: uploads the Boys-function
+ * interpolation table and the Hermite recursion tables (a few MB of device
+ * memory held until process exit) and sets kernel attributes.  Every compute
+ * call does this lazily on first use of a device; calling it up front keeps
+ * the allocation out of timed or captured regions.  Synchronous. */
+eri4_status eri4_init(void);
+
+/*
+ * eri4_batch -- (ab|cd) for nquartets independent shell quartets of one class
+ * (la lb|lc ld), by the matrix form of McMurchie-Davidson (Sec. 2, eqs.
+ * (abcd_to_hermite), (ab_to_hermite), (cd_to_hermite)): Boys function, Hermite
+ * integrals [r]^(m) by eq. (md1), [p|q] by eq. (pq), then the bra transform
+ * [ab|q] = sum_p E_ab^p [p|q] and the ket transform (ab|cd) = sum_q E_cd^q [ab|q]
+ * as FP64 matrix products with the primitive contraction folded into the
+ * product dimensions (Sec. 3, the batched-GEMM paragraph).  FP64 throughout.
+ *
+ *   la..ld     0..ERI4_MAX_L
+ *   nquartets  >= 0 (0: nothing is enqueued, pointers may be NULL)
+ *   centers    device double [nquartets][4][3]       shell centres A, B, C, D (Bohr)
+ *   exponents  device double [nquartets][4][kmax]    z_p > 0 for p < nprim
+ *   coeffs     device double [nquartets][4][kmax]    c_p for p < nprim
+ *   nprim      device int32  [nquartets][4]          contraction lengths, 1..kmax
+ *   kmax       1..ERI4_MAX_K, the padded length of the exponent/coefficient rows
+ *   out        device double [nquartets][Na][Nb][Nc][Nd], row-major, quartets in
+ *              input order; every element is written
+ *   stream     hipStream_t
+ * Entries p >= nprim of exponents/coeffs are never read.
+ * Returns ERI4_SUCCESS, ERI4_ERROR_INVALID_ARGUMENT (bad l, sizes or NULL
+ * pointers), ERI4_ERROR_UNSUPPORTED (l > ERI4_MAX_L), ERI4_ERROR_HIP or
+ * ERI4_ERROR_OUT_OF_MEMORY (set-up on first use).
+ */
+eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets,
+                       const double* centers, const double* exponents, const double* coeffs,
+                       const int32_t* nprim, int kmax, double* out, hipStream_t stream);
+
+/*
+ * Stage entry points.  They run the same device code the fused eri4_batch
+ * kernel runs for one stage, so each stage can be checked on its own.
+ */
+
+/* Boys function of eq. (boys), F_m(T) = int_0^1 y^(2m) exp(-T y^2) dy, for
+ * m = 0..mmax (mmax 0..ERI4_MAX_BOYS_M) at n arguments T >= 0.
+ *   T  device double [n];   F  device double [n][mmax+1]
+ * Negative or non-finite T give NaN rows. */
+eri4_status eri4_boys(int mmax, int64_t n, const double* T, double* F, hipStream_t stream);
+
+/* Hermite integrals R[t][u][v] = [r]^(0) (Sec. 2, from [0]^(m) and eq. (md1)) for
+ * n primitive pairs-of-pairs, with total order t+u+v <= L (0..4*ERI4_MAX_L).
+ *   zp, zq  device double [n]      zeta_p = za+zb, zeta_q = zc+zd (> 0)
+ *   P, Q    device double [n][3]   product centres R_p, R_q
+ *   R       device double [n][L+1][L+1][L+1]; entries with t+u+v > L are 0
+ * No Gaussian-product prefactor or contraction coefficient is applied. */
+eri4_status eri4_hermite_r(int L, int64_t n, const double* zp, const double* zq,
+                           const double* P, const double* Q, double* R, hipStream_t stream);
+
+/* Hermite expansion coefficients of eq. (cart2herm-2) for n primitive pairs,
+ * from the two recursions that follow it with (E)^0_00 = 1:
+ *   za, zb  device double [n];  A, B  device double [n][3]
+ *   E       device double [n][3][la+1][lb+1][la+lb+1]   (axis x, y, z; entries
+ *           with t > a+b are 0).  la, lb in 0..7. */
+eri4_status eri4_hermite_e(int la, int lb, int64_t n, const double* za, const double* zb,
+                           const double* A, const double* B, double* E, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ERI4_H */

@@ -1,0 +1,778 @@
+// eri4.hip -- gfx950 kernels and the C ABI of liberi4.
+//
+// (ab|cd) over contracted Cartesian Gaussians by the matrix form of the
+// McMurchie-Davidson scheme (Asadchev & Valeev, Sec. 2 and Sec. 3):
+//
+//   [0]^(m) = (-2 rho)^m 2 pi^(5/2) / (zp zq sqrt(zp+zq)) F_m(rho |P-Q|^2)
+//   [r + 1_i]^(m) = r_i [r - 1_i]^(m+1) + (P_i - Q_i) [r]^(m+1)      eq. (md1)
+//   [p|q] = (-1)^|q| [p+q]^(0)                                       eq. (pq)
+//   [ab|q] = sum_p E_ab^p [p|q]                                      eq. (ab_to_hermite)
+//   (ab|cd) = sum_q E_cd^q [ab|q]                                    eq. (cd_to_hermite)
+//
+// One workgroup (8 waves) owns one quartet and a tile of RB*16 bra rows ab.
+// For each ket primitive pair kl it accumulates, over the bra primitive pairs
+// ij, the first transform [ab_tile|q] in FP64 MFMA registers (the contraction
+// is folded into the product dimension, Sec. 3), moves that tile to LDS and
+// applies the second transform straight into the output.  [p|q] is never
+// stored: its entries are gathered from the R box in LDS, whose linear layout
+// turns the index p+q into an address sum.  E entries are products of three
+// 1-d tables in LDS.  The sign (-1)^|q| is folded into the ket tables and the
+// Gaussian-product prefactors and contraction coefficients into [0]^(m).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "eri4.h"
+#include "eri4_internal.h"
+
+namespace eri4 {
+void make_boys_table(std::vector<double>& tab);
+void make_rtabs(std::vector<uint32_t>& tab, std::vector<int>& start);
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxLdsBytes = 160 * 1024;
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  // D[16x16] += A[16x4] B[4x16]; lane l holds A[l%16][l/16], B[l/16][l%16],
+  // and D rows 4j + l/16, column l%16 in element j.
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// F_m(T), eq. (boys): Taylor expansion on the grid below kBoysTMax, asymptotic
+// form above.  Negative T gives NaN.
+__device__ double boys_fm(int m, double T, const double* __restrict__ tab) {
+  if (T >= 0.0 && T < kBoysTMax) {
+    const int i = (int)(T * kBoysInvH + 0.5);
+    const double x = (double)i * kBoysH - T;  // -(T - T_i), exact
+    const double* r = tab + (size_t)i * kBoysCols + m;
+    double s = r[kBoysJ];
+#pragma unroll
+    for (int j = kBoysJ - 1; j >= 0; --j) s = fma(s * x, 1.0 / (double)(j + 1), r[j]);
+    return s;
+  }
+  if (!(T >= 0.0)) return __builtin_nan("");
+  // F_m(T) = Gamma(m+1/2) / (2 T^(m+1/2)); the neglected incomplete-gamma part
+  // is below 1e-20 relative for T >= kBoysTMax and m <= kMaxL.
+  return tab[(size_t)kBoysAsymRow * kBoysCols + m] / (pow(T, (double)m) * sqrt(T));
+}
+
+// One step of the E recursions that follow eq. (cart2herm-2):
+//   E^t <- (1/(2 zp)) E^(t-1) + c E^t + (t+1) E^(t+1),  c = P-A or P-B.
+__device__ __forceinline__ void etab_step(double (&e)[16], double h, double c) {
+  double prev = 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const double cur = e[t];
+    const double nxt = (t + 1 < 16) ? e[t + 1] : 0.0;
+    e[t] = h * prev + c * cur + (double)(t + 1) * nxt;
+    prev = cur;
+  }
+}
+
+// Three 1-d tables (x, y, z) of one primitive pair into LDS, one wave:
+// row (a,b) of axis i at E + i*taxis + (a*(lb+1)+b)*trow, entries t < trow
+// (t > a+b are 0, in particular the last one).  Each axis ends with an all-zero
+// row at row index (la+1)*(lb+1), used for padding rows.  alt_sign multiplies
+// entry t by (-1)^t (the ket side of eq. (pq)).
+__device__ void build_etab(double* E, int la, int lb, int trow, int taxis, double h,
+                           const double* PA, const double* PB, bool alt_sign, int lane) {
+  const int na = la + 1;
+  for (int j = lane; j < 3 * trow; j += 64) {  // the all-zero padding rows
+    const int axis = j / trow;
+    E[axis * taxis + na * (lb + 1) * trow + (j - axis * trow)] = 0.0;
+  }
+  if (lane < 3 * na) {
+    const int axis = lane / na;
+    const int a = lane - axis * na;
+    const double pa = PA[axis], pb = PB[axis];
+    double e[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) e[t] = (t == 0) ? 1.0 : 0.0;
+    for (int s = 0; s < a; ++s) etab_step(e, h, pa);
+    double* base = E + axis * taxis + a * (lb + 1) * trow;
+    for (int b = 0; b <= lb; ++b) {
+      double* row = base + b * trow;
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (t < trow) row[t] = (alt_sign && (t & 1)) ? -e[t] : e[t];
+      if (b < lb) etab_step(e, h, pb);
+    }
+  }
+}
+
+// Hermite index table: ordinal -> (t,u,v) in lexicographic order over
+// t+u+v <= Lh, packed t | u<<8 | v<<16 together with the offset in the R box.
+// Entries n..n_alloc-1 are padding: (Lh+1, 0, 0) (an E index whose value is 0)
+// and box offset 0.
+__device__ void build_htab(int2* tab, int Lh, int n, int n_alloc, int S1, int S2, int tid) {
+  const int ncol = (Lh + 1) * (Lh + 2) / 2;
+  for (int c = tid; c < ncol; c += kThreads) {
+    int t = 0, rem = c;
+    while (rem >= Lh - t + 1) {
+      rem -= Lh - t + 1;
+      ++t;
+    }
+    const int u = rem;
+    // triples before column (t,u): all with a smaller t, then columns u' < u of this t
+    const int first = (nherm(Lh) - nherm(Lh - t)) + u * (2 * (Lh - t) + 3 - u) / 2;
+    for (int v = 0; v <= Lh - t - u; ++v)
+      tab[first + v] = make_int2(t | (u << 8) | (v << 16), t * S2 + u * S1 + v);
+  }
+  for (int i = n + tid; i < n_alloc; i += kThreads) tab[i] = make_int2(Lh + 1, 0);
+}
+
+// Cartesian component index -> (x, y, z) for shell l (order ax = l..0, ay = l-ax..0).
+__device__ __forceinline__ void cart_of(int l, int i, int& x, int& y, int& z) {
+  int n = 0;
+  while ((n + 1) * (n + 2) / 2 <= i) ++n;
+  z = i - n * (n + 1) / 2;
+  y = n - z;
+  x = l - n;
+}
+
+// [r]^(0) for |r| <= L in the (L+1)^3 LDS box, by eq. (md1) for decreasing m,
+// overwriting [r]^(m+1) with [r]^(m).  Each level is computed into registers
+// (up to kRPerThread entries per thread), then written after a barrier.
+// baseM[m] holds [0]^(m); PQ (3 doubles, LDS) is P - Q.  The recursion table
+// rt is re-read every level so that its decoded form is not kept live.
+__device__ void hermite_r_box(double* box, const double* baseM, int L, int S1, int S2,
+                              const double* PQ, const uint32_t* __restrict__ rt, int tid) {
+  if (tid == 0) box[0] = baseM[L];
+  __syncthreads();
+  for (int m = L - 1; m >= 0; --m) {
+    const int nact = nherm(L - m);
+    const uint32_t* rtm = rt;
+    asm volatile("" : "+s"(rtm));  // opaque: reload the entries every level
+    double nv[kRPerThread];
+#pragma unroll
+    for (int k = 0; k < kRPerThread; ++k) {
+      const int e = tid + k * kThreads;
+      nv[k] = 0.0;
+      if (e < nact) {
+        if (e == 0) {
+          nv[k] = baseM[m];
+        } else {
+          const uint32_t w = rtm[e];
+          const int tgt = (int)(w & 0xffffu);
+          const int dir = (int)((w >> 16) & 3u);
+          const int ri = (int)((w >> 18) & 63u);
+          const int stride = dir == 0 ? S2 : (dir == 1 ? S1 : 1);
+          const int o1 = tgt - stride;
+          const int o2 = ri >= 2 ? o1 - stride : o1;
+          nv[k] = PQ[dir] * box[o1] + (double)(ri - 1) * box[o2];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRPerThread; ++k) {
+      const int e = tid + k * kThreads;
+      if (e < nact) box[rtm[e] & 0xffffu] = nv[k];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused kernel
+// ---------------------------------------------------------------------------
+
+// Primitive-pair data, stored in LDS as 11 doubles:
+//   [0] z = za + zb, [1] w = ca cb exp(-za zb / z |A-B|^2) (Gaussian product
+//   prefactor times the two contraction coefficients), [2..4] P, [5..7] P-A, [8..10] P-B.
+constexpr int kPairDoubles = 11;
+
+__device__ __forceinline__ void make_pair(double* out, double za, double zb, double ca, double cb,
+                                          const double* A, const double* B) {
+  const double z = za + zb;
+  const double iz = 1.0 / z;
+  double ab2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    // P - A = zb (B - A) / z and P - B = za (A - B) / z, formed without the
+    // cancellation of subtracting two absolute positions
+    const double dd = A[i] - B[i];
+    out[2 + i] = (za * A[i] + zb * B[i]) * iz;
+    out[5 + i] = -zb * iz * dd;
+    out[8 + i] = za * iz * dd;
+    ab2 += dd * dd;
+  }
+  out[0] = z;
+  out[1] = ca * cb * exp(-za * zb * iz * ab2);
+}
+
+template <int RB, int C1, int C2G>
+__global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
+    const ClassParams cp, const double* __restrict__ boys_tab, const uint32_t* __restrict__ rtab_L,
+    const double* __restrict__ centers, const double* __restrict__ exps,
+    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, double* __restrict__ out,
+    int64_t q0) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t q = q0 + blockIdx.x / cp.nrt;
+  const int rt = blockIdx.x % cp.nrt;
+  const int kmax = cp.kmax;
+
+  double* sh = (double*)(lds + cp.o_shell);
+  int* shn = (int*)(sh + 12 + 8 * kmax);
+  double* baseM = (double*)(lds + cp.o_base);
+  int2* ptab = (int2*)(lds + cp.o_ptab);
+  int2* qtab = (int2*)(lds + cp.o_qtab);
+  double* box = (double*)(lds + cp.o_union);
+  double* brae = (double*)(lds + cp.o_brae);
+  double* X = (double*)(lds + cp.o_union);
+  double* kete = (double*)(lds + cp.o_kete);
+
+  // shell data of this quartet
+  if (tid < 12) {
+    sh[tid] = centers[q * 12 + tid];
+  } else if (tid < 12 + 8 * kmax) {
+    const int j = tid - 12;
+    sh[tid] = (j < 4 * kmax) ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)];
+  } else if (tid >= 256 && tid < 260) {
+    shn[tid - 256] = nprim[q * 4 + (tid - 256)];
+  }
+  build_htab(ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, tid);
+  build_htab(qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, tid);
+  __syncthreads();
+
+  const int Ka = shn[0], Kb = shn[1], Kc = shn[2], Kd = shn[3];
+  const int row0 = rt * RB * 16;
+  if (Ka < 1 || Ka > kmax || Kb < 1 || Kb > kmax || Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax) {
+    const int nrows = min(RB * 16, cp.nab - row0);
+    double* o = out + q * (int64_t)cp.nab * cp.ncd + (int64_t)row0 * cp.ncd;
+    for (int i = tid; i < nrows * cp.ncd; i += kThreads) o[i] = __builtin_nan("");
+    return;
+  }
+  const double* A = sh;
+  const double* B = sh + 3;
+  const double* C = sh + 6;
+  const double* D = sh + 9;
+  const double* ex = sh + 12;
+  const double* co = sh + 12 + 4 * kmax;
+
+  // bra rows of this lane (A operand of the first transform)
+  int rowx[RB], rowy[RB], rowz[RB];
+  bool rbv[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    rbv[r] = row0 + r * 16 < cp.nab;
+    const int ab = row0 + r * 16 + (lane & 15);
+    if (ab < cp.nab) {
+      const int ia = ab / cp.nb, ib = ab - ia * cp.nb;
+      int ax, ay, az, bx, by, bz;
+      cart_of(cp.la, ia, ax, ay, az);
+      cart_of(cp.lb, ib, bx, by, bz);
+      rowx[r] = (ax * (cp.lb + 1) + bx) * cp.tbrow;
+      rowy[r] = cp.tbaxis + (ay * (cp.lb + 1) + by) * cp.tbrow;
+      rowz[r] = 2 * cp.tbaxis + (az * (cp.lb + 1) + bz) * cp.tbrow;
+    } else {
+      const int zr = (cp.la + 1) * (cp.lb + 1) * cp.tbrow;
+      rowx[r] = zr;
+      rowy[r] = cp.tbaxis + zr;
+      rowz[r] = 2 * cp.tbaxis + zr;
+    }
+  }
+  // [ab|q] columns of this lane (B operand of the first transform)
+  int offq[C1];
+#pragma unroll
+  for (int c = 0; c < C1; ++c) {
+    const int cb = wave + 8 * c;
+    offq[c] = (cb < cp.nqb) ? qtab[cb * 16 + (lane & 15)].y : 0;
+  }
+  const int ncbw = (wave < cp.ncdb) ? (cp.ncdb - wave + 7) / 8 : 0;  // output column blocks of this wave
+
+  const double pref = 2.0 * pow(M_PI, 2.5);
+  const int64_t qoff = q * (int64_t)cp.nab * cp.ncd;
+  double* kpair = baseM + 32;
+  double* bpair = kpair + 16;
+  double* pqv = bpair + 16;
+
+  for (int kl = 0; kl < Kc * Kd; ++kl) {
+    if (tid == 0) {
+      const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
+      make_pair(kpair, ex[2 * kmax + k], ex[3 * kmax + l], co[2 * kmax + k], co[3 * kmax + l], C, D);
+    }
+    d4 acc1[RB][C1];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c = 0; c < C1; ++c) acc1[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
+
+    for (int ij = 0; ij < Ka * Kb; ++ij) {
+      if (tid == 64) {
+        const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
+        make_pair(bpair, ex[i], ex[kmax + j], co[i], co[kmax + j], A, B);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        if (lane < 3) pqv[lane] = bpair[2 + lane] - kpair[2 + lane];
+        if (lane <= cp.L) {
+          const double zp = bpair[0], zq = kpair[0];
+          const double zs = zp + zq;
+          const double rho = zp * zq / zs;
+          double r2 = 0.0;
+#pragma unroll
+          for (int x = 0; x < 3; ++x) {
+            const double d = bpair[2 + x] - kpair[2 + x];
+            r2 += d * d;
+          }
+          const double F = boys_fm(lane, rho * r2, boys_tab);
+          double pw = 1.0;
+          for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
+          baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (bpair[1] * kpair[1]) * F;
+        }
+      } else if (wave == 1) {
+        build_etab(brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / bpair[0], bpair + 5, bpair + 8, false, lane);
+      }
+      __syncthreads();
+      hermite_r_box(box, baseM, cp.L, cp.S1, cp.S2, pqv, rtab_L, tid);
+
+      // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
+      for (int kk = 0; kk < cp.np4; kk += 4) {
+        const int2 pt = ptab[kk + (lane >> 4)];
+        const int tp = pt.x & 0xff, up = (pt.x >> 8) & 0xff, vp = pt.x >> 16;
+        double a[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) a[r] = brae[rowx[r] + tp] * brae[rowy[r] + up] * brae[rowz[r] + vp];
+#pragma unroll
+        for (int c = 0; c < C1; ++c) {
+          if (wave + 8 * c < cp.nqb) {
+            const double b = box[pt.y + offq[c]];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+              if (rbv[r]) acc1[r][c] = mfma16(a[r], b, acc1[r][c]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // [ab_tile|q] -> LDS (aliases the R box), ket tables for kl
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c = 0; c < C1; ++c) {
+        const int cb = wave + 8 * c;
+        if (cb < cp.nqb && rbv[r]) {
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            X[(r * 16 + 4 * jj + (lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = acc1[r][c][jj];
+        }
+      }
+    if (wave == 0)
+      build_etab(kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / kpair[0], kpair + 5, kpair + 8, true, lane);
+    __syncthreads();
+
+    // second transform: (ab|cd) += sum_q E_cd^q [ab|q], written to HBM
+    for (int g0 = 0; g0 < ncbw; g0 += C2G) {
+      int kx[C2G], ky[C2G], kz[C2G];
+      bool cv[C2G];
+#pragma unroll
+      for (int c = 0; c < C2G; ++c) {
+        cv[c] = g0 + c < ncbw;
+        const int cd = (wave + 8 * (g0 + c)) * 16 + (lane & 15);
+        if (cv[c] && cd < cp.ncd) {
+          const int ic = cd / cp.nd, id = cd - (cd / cp.nd) * cp.nd;
+          int cx, cy, cz, dx, dy, dz;
+          cart_of(cp.lc, ic, cx, cy, cz);
+          cart_of(cp.ld, id, dx, dy, dz);
+          kx[c] = (cx * (cp.ld + 1) + dx) * cp.tkrow;
+          ky[c] = cp.tkaxis + (cy * (cp.ld + 1) + dy) * cp.tkrow;
+          kz[c] = 2 * cp.tkaxis + (cz * (cp.ld + 1) + dz) * cp.tkrow;
+        } else {
+          const int zr = (cp.lc + 1) * (cp.ld + 1) * cp.tkrow;
+          kx[c] = zr;
+          ky[c] = cp.tkaxis + zr;
+          kz[c] = 2 * cp.tkaxis + zr;
+        }
+      }
+      d4 acc2[RB][C2G];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < C2G; ++c) acc2[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
+      for (int kk = 0; kk < cp.nq4; kk += 4) {
+        const int qq = kk + (lane >> 4);
+        const int pk = qtab[qq].x;
+        const int tq = pk & 0xff, uq = (pk >> 8) & 0xff, vq = pk >> 16;
+        double a[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) a[r] = X[(r * 16 + (lane & 15)) * cp.xs + qq];
+#pragma unroll
+        for (int c = 0; c < C2G; ++c) {
+          if (cv[c]) {
+            const double b = kete[kx[c] + tq] * kete[ky[c] + uq] * kete[kz[c] + vq];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+              if (rbv[r]) acc2[r][c] = mfma16(a[r], b, acc2[r][c]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < C2G; ++c) {
+          if (!cv[c] || !rbv[r]) continue;
+          const int cd = (wave + 8 * (g0 + c)) * 16 + (lane & 15);
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int ab = row0 + r * 16 + 4 * jj + (lane >> 4);
+            if (ab < cp.nab && cd < cp.ncd) {
+              double* o = out + qoff + (int64_t)ab * cp.ncd + cd;
+              if (kl == 0)
+                __builtin_nontemporal_store(acc2[r][c][jj], o);
+              else
+                *o += acc2[r][c][jj];
+            }
+          }
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage kernels (same device code as the fused kernel)
+// ---------------------------------------------------------------------------
+
+__global__ void boys_kernel(int mmax, int64_t n, const double* __restrict__ T, double* __restrict__ F,
+                            const double* __restrict__ tab) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = n * (mmax + 1);
+  if (g >= total) return;
+  const int64_t i = g / (mmax + 1);
+  const int m = (int)(g - i * (mmax + 1));
+  F[g] = boys_fm(m, T[i], tab);
+}
+
+__global__ __launch_bounds__(kThreads, 1) void hermite_r_kernel(
+    int L, const double* __restrict__ zp, const double* __restrict__ zq, const double* __restrict__ P,
+    const double* __restrict__ Q, double* __restrict__ R, const double* __restrict__ boys_tab,
+    const uint32_t* __restrict__ rtab_L) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* baseM = (double*)lds;
+  double* box = baseM + 32;
+  const int tid = threadIdx.x;
+  const int64_t it = blockIdx.x;
+  const int n1 = L + 1, S1 = n1, S2 = n1 * n1;
+  const double a = zp[it], b = zq[it];
+  double PQ[3];
+  for (int x = 0; x < 3; ++x) PQ[x] = P[it * 3 + x] - Q[it * 3 + x];
+  double* pq = baseM + 32 + (L + 1) * (L + 1) * (L + 1);
+  if (tid < 3) pq[tid] = PQ[tid];
+  if (tid <= L) {
+    const double rho = a * b / (a + b);
+    const double T = rho * (PQ[0] * PQ[0] + PQ[1] * PQ[1] + PQ[2] * PQ[2]);
+    double pw = 1.0;
+    for (int mm = 0; mm < tid; ++mm) pw *= -2.0 * rho;
+    baseM[tid] = pw * (2.0 * pow(M_PI, 2.5) / (a * b * sqrt(a + b))) * boys_fm(tid, T, boys_tab);
+  }
+  __syncthreads();
+  hermite_r_box(box, baseM, L, S1, S2, pq, rtab_L, tid);
+  double* o = R + it * (int64_t)n1 * n1 * n1;
+  for (int e = tid; e < n1 * n1 * n1; e += kThreads) {
+    const int t = e / S2, u = (e / S1) % n1, v = e % n1;
+    o[e] = (t + u + v <= L) ? box[e] : 0.0;
+  }
+}
+
+__global__ void hermite_e_kernel(int la, int lb, const double* __restrict__ za, const double* __restrict__ zb,
+                                 const double* __restrict__ A, const double* __restrict__ B,
+                                 double* __restrict__ E) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* tabs = (double*)lds;
+  const int lane = threadIdx.x;
+  const int64_t it = blockIdx.x;
+  const int trow = la + lb + 2;
+  const int taxis = ((la + 1) * (lb + 1) + 1) * trow;
+  double* pair = tabs + 3 * taxis;
+  if (lane == 0) {
+    double Av[3], Bv[3];
+    for (int x = 0; x < 3; ++x) {
+      Av[x] = A[it * 3 + x];
+      Bv[x] = B[it * 3 + x];
+    }
+    make_pair(pair, za[it], zb[it], 1.0, 1.0, Av, Bv);
+  }
+  __syncthreads();
+  build_etab(tabs, la, lb, trow, taxis, 0.5 / pair[0], pair + 5, pair + 8, false, lane);
+  __syncthreads();
+  const int nt = la + lb + 1;
+  const int per_axis = (la + 1) * (lb + 1) * nt;
+  double* o = E + it * 3 * per_axis;
+  for (int e = lane; e < 3 * per_axis; e += blockDim.x) {
+    const int axis = e / per_axis, rem = e - axis * per_axis;
+    const int ab = rem / nt, t = rem - ab * nt;
+    o[e] = tabs[axis * taxis + ab * trow + t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+thread_local std::string g_err;
+
+eri4_status fail(eri4_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+struct DeviceState {
+  bool ready = false;
+  double* boys = nullptr;
+  uint32_t* rtab = nullptr;
+  int rstart[kMaxL + 2] = {0};
+};
+
+std::mutex g_mu;
+std::vector<DeviceState> g_dev;
+
+#define HIP_TRY(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(ERI4_ERROR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+template <int RB, int C1>
+eri4_status set_attr_one() {
+  HIP_TRY(hipFuncSetAttribute((const void*)eri4_fused_kernel<RB, C1, 4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes));
+  return ERI4_SUCCESS;
+}
+
+eri4_status set_attrs() {
+  eri4_status s;
+#define ONE(RB, C1) if ((s = set_attr_one<RB, C1>()) != ERI4_SUCCESS) return s;
+  ONE(1, 1) ONE(1, 2) ONE(1, 3) ONE(1, 4) ONE(2, 1) ONE(2, 2) ONE(2, 3) ONE(2, 4)
+#undef ONE
+  HIP_TRY(hipFuncSetAttribute((const void*)hermite_r_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxLdsBytes));
+  return ERI4_SUCCESS;
+}
+
+eri4_status ensure_device(DeviceState** st) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+  DeviceState& d = g_dev[dev];
+  if (!d.ready) {
+    static std::vector<double> boys;
+    static std::vector<uint32_t> rt;
+    static std::vector<int> rs;
+    if (boys.empty()) {
+      make_boys_table(boys);
+      make_rtabs(rt, rs);
+    }
+    if ((int)rt.size() != kRtabTotal) return fail(ERI4_ERROR_INTERNAL, "recursion table size mismatch");
+    if (hipMalloc(&d.boys, boys.size() * sizeof(double)) != hipSuccess)
+      return fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation of the Boys table failed");
+    if (hipMalloc(&d.rtab, rt.size() * sizeof(uint32_t)) != hipSuccess)
+      return fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation of the recursion tables failed");
+    HIP_TRY(hipMemcpy(d.boys, boys.data(), boys.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.rtab, rt.data(), rt.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    for (int L = 0; L <= kMaxL + 1; ++L) d.rstart[L] = rs[L];
+    eri4_status s = set_attrs();
+    if (s != ERI4_SUCCESS) return s;
+    d.ready = true;
+  }
+  *st = &d;
+  return ERI4_SUCCESS;
+}
+
+int align16(int x) { return (x + 15) & ~15; }
+
+// Class parameters and LDS layout for a tile of rb*16 bra rows.
+ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb) {
+  ClassParams p{};
+  p.la = la; p.lb = lb; p.lc = lc; p.ld = ld;
+  p.na = ncart(la); p.nb = ncart(lb); p.nc = ncart(lc); p.nd = ncart(ld);
+  p.nab = p.na * p.nb; p.ncd = p.nc * p.nd;
+  p.Lb = la + lb; p.Lk = lc + ld; p.L = p.Lb + p.Lk;
+  p.np = nherm(p.Lb); p.nq = nherm(p.Lk);
+  p.np4 = (p.np + 3) & ~3; p.nq4 = (p.nq + 3) & ~3;
+  p.nqb = (p.nq + 15) / 16;
+  p.ncdb = (p.ncd + 15) / 16;
+  p.nrt = (p.nab + 16 * rb - 1) / (16 * rb);
+  p.S1 = p.L + 1; p.S2 = (p.L + 1) * (p.L + 1);
+  p.tbrow = p.Lb + 2; p.tkrow = p.Lk + 2;
+  p.tbaxis = ((la + 1) * (lb + 1) + 1) * p.tbrow;
+  p.tkaxis = ((lc + 1) * (ld + 1) + 1) * p.tkrow;
+  p.xs = 16 * p.nqb + 2;
+  p.kmax = kmax;
+  int off = 0;
+  p.o_shell = off; off = align16(off + (12 + 8 * kmax) * 8 + 4 * 4);
+  p.o_base = off;  off = align16(off + 96 * 8);  // [0]^(m), ket pair, bra pair, P-Q
+  p.o_ptab = off;  off = align16(off + p.np4 * 8);
+  p.o_qtab = off;  off = align16(off + 16 * p.nqb * 8);
+  p.o_union = off;
+  const int box_b = (p.L + 1) * (p.L + 1) * (p.L + 1) * 8;
+  const int ph1 = align16(box_b) + 3 * p.tbaxis * 8;
+  const int xb = align16(rb * 16 * p.xs * 8);
+  const int ph2 = xb + 3 * p.tkaxis * 8;
+  p.o_brae = off + align16(box_b);
+  p.o_kete = off + xb;
+  off = align16(off + (ph1 > ph2 ? ph1 : ph2));
+  p.lds_bytes = off;
+  return p;
+}
+
+template <int RB, int C1>
+hipError_t launch_fused(const ClassParams& p, dim3 grid, hipStream_t s, const DeviceState* d,
+                        const double* c, const double* e, const double* co, const int32_t* np, double* out,
+                        int64_t q0) {
+  hipLaunchKernelGGL((eri4_fused_kernel<RB, C1, 4>), grid, dim3(kThreads), p.lds_bytes, s, p, d->boys,
+                     d->rtab + d->rstart[p.L], c, e, co, np, out, q0);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace eri4
+
+using namespace eri4;
+
+extern "C" {
+
+int eri4_ncart(int l) { return l < 0 ? -1 : ncart(l); }
+
+int64_t eri4_quartet_size(int la, int lb, int lc, int ld) {
+  if (la < 0 || lb < 0 || lc < 0 || ld < 0) return -1;
+  return (int64_t)ncart(la) * ncart(lb) * ncart(lc) * ncart(ld);
+}
+
+const char* eri4_last_error(void) { return g_err.c_str(); }
+
+const char* eri4_version(void) { return "eri4 0.1 (gfx950, FP64 MFMA matrix McMurchie-Davidson)"; }
+
+eri4_status eri4_init(void) {
+  g_err.clear();
+  DeviceState* d;
+  return ensure_device(&d);
+}
+
+eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                       const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                       double* out, hipStream_t stream) {
+  g_err.clear();
+  if (la < 0 || lb < 0 || lc < 0 || ld < 0)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "angular momenta must be >= 0 (got %d %d %d %d)", la, lb, lc, ld);
+  if (la > ERI4_MAX_L || lb > ERI4_MAX_L || lc > ERI4_MAX_L || ld > ERI4_MAX_L)
+    return fail(ERI4_ERROR_UNSUPPORTED, "angular momentum above %d is not supported (got %d %d %d %d)",
+                ERI4_MAX_L, la, lb, lc, ld);
+  if (nquartets < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "nquartets must be >= 0");
+  if (kmax < 1 || kmax > ERI4_MAX_K)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "kmax must be in 1..%d (got %d)", ERI4_MAX_K, kmax);
+  if (nquartets == 0) return ERI4_SUCCESS;
+  if (!centers || !exponents || !coeffs || !nprim || !out)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  DeviceState* d;
+  eri4_status s = ensure_device(&d);
+  if (s != ERI4_SUCCESS) return s;
+  int rb = 2;
+  ClassParams p = make_params(la, lb, lc, ld, kmax, rb);
+  if (p.lds_bytes > kMaxLdsBytes) {
+    rb = 1;
+    p = make_params(la, lb, lc, ld, kmax, rb);
+  }
+  if (p.lds_bytes > kMaxLdsBytes)
+    return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) needs %d bytes of LDS", la, lb, lc, ld, p.lds_bytes);
+  const int c1 = (p.nqb + 7) / 8;
+  if (c1 > 4) return fail(ERI4_ERROR_INTERNAL, "no kernel variant for %d column blocks", p.nqb);
+  const int64_t max_blocks = (int64_t)1 << 30;
+  const int64_t qchunk = max_blocks / p.nrt;
+  for (int64_t q0 = 0; q0 < nquartets; q0 += qchunk) {
+    const int64_t nq = (nquartets - q0 < qchunk) ? nquartets - q0 : qchunk;
+    const dim3 grid((unsigned)(nq * p.nrt));
+    hipError_t e = hipSuccess;
+    switch (rb * 10 + c1) {
+      case 11: e = launch_fused<1, 1>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
+      case 12: e = launch_fused<1, 2>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
+      case 13: e = launch_fused<1, 3>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
+      case 14: e = launch_fused<1, 4>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
+      case 21: e = launch_fused<2, 1>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
+      case 22: e = launch_fused<2, 2>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
+      case 23: e = launch_fused<2, 3>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
+      case 24: e = launch_fused<2, 4>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
+      default: return fail(ERI4_ERROR_INTERNAL, "no kernel variant");
+    }
+    if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
+  }
+  return ERI4_SUCCESS;
+}
+
+eri4_status eri4_boys(int mmax, int64_t n, const double* T, double* F, hipStream_t stream) {
+  g_err.clear();
+  if (mmax < 0 || mmax > ERI4_MAX_BOYS_M)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "mmax must be in 0..%d", ERI4_MAX_BOYS_M);
+  if (n < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "n must be >= 0");
+  if (n == 0) return ERI4_SUCCESS;
+  if (!T || !F) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  DeviceState* d;
+  eri4_status s = ensure_device(&d);
+  if (s != ERI4_SUCCESS) return s;
+  const int64_t total = n * (mmax + 1);
+  const int64_t nb = (total + 255) / 256;
+  if (nb > ((int64_t)1 << 31) - 1) return fail(ERI4_ERROR_INVALID_ARGUMENT, "n too large");
+  hipLaunchKernelGGL(boys_kernel, dim3((unsigned)nb), dim3(256), 0, stream, mmax, n, T, F, d->boys);
+  HIP_TRY(hipGetLastError());
+  return ERI4_SUCCESS;
+}
+
+eri4_status eri4_hermite_r(int L, int64_t n, const double* zp, const double* zq, const double* P,
+                           const double* Q, double* R, hipStream_t stream) {
+  g_err.clear();
+  if (L < 0 || L > 4 * ERI4_MAX_L)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "L must be in 0..%d", 4 * ERI4_MAX_L);
+  if (n < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "n must be >= 0");
+  if (n == 0) return ERI4_SUCCESS;
+  if (!zp || !zq || !P || !Q || !R) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  if (n > ((int64_t)1 << 31) - 1) return fail(ERI4_ERROR_INVALID_ARGUMENT, "n too large");
+  DeviceState* d;
+  eri4_status s = ensure_device(&d);
+  if (s != ERI4_SUCCESS) return s;
+  const int lds = (32 + (L + 1) * (L + 1) * (L + 1) + 4) * 8;
+  hipLaunchKernelGGL(hermite_r_kernel, dim3((unsigned)n), dim3(kThreads), lds, stream, L, zp, zq, P, Q, R,
+                     d->boys, d->rtab + d->rstart[L]);
+  HIP_TRY(hipGetLastError());
+  return ERI4_SUCCESS;
+}
+
+eri4_status eri4_hermite_e(int la, int lb, int64_t n, const double* za, const double* zb, const double* A,
+                           const double* B, double* E, hipStream_t stream) {
+  g_err.clear();
+  if (la < 0 || lb < 0 || la > kTableLMax || lb > kTableLMax)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "la, lb must be in 0..%d", kTableLMax);
+  if (n < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "n must be >= 0");
+  if (n == 0) return ERI4_SUCCESS;
+  if (!za || !zb || !A || !B || !E) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  if (n > ((int64_t)1 << 31) - 1) return fail(ERI4_ERROR_INVALID_ARGUMENT, "n too large");
+  DeviceState* d;
+  eri4_status s = ensure_device(&d);
+  if (s != ERI4_SUCCESS) return s;
+  const int trow = la + lb + 2;
+  const int lds = (3 * ((la + 1) * (lb + 1) + 1) * trow + 16) * 8;
+  hipLaunchKernelGGL(hermite_e_kernel, dim3((unsigned)n), dim3(64), lds, stream, la, lb, za, zb, A, B, E);
+  HIP_TRY(hipGetLastError());
+  return ERI4_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// eri4_internal.h -- constants and parameter blocks shared by the host side and
+// the gfx950 kernels of liberi4.  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+namespace eri4 {
+
+// Largest l per shell the index tables are sized for, and the largest total
+// Hermite order L = la+lb+lc+ld (Boys orders 0..L).
+constexpr int kTableLMax = 7;
+constexpr int kMaxL = 4 * kTableLMax;  // 28
+
+// Boys-function interpolation grid (Sec. 2, eq. (boys)): F_k(T_i) at
+// T_i = i * kBoysH for i < kBoysRows, k < kBoysCols, used as a Taylor expansion
+// F_m(T_i + d) = sum_j F_{m+j}(T_i) (-d)^j / j!, j <= kBoysJ.  kBoysH is a
+// power of two so that T_i and d = T - T_i are exact.  Beyond kBoysTMax the
+// asymptotic form F_m(T) = (2m-1)!! / 2^(m+1) sqrt(pi / T^(2m+1)) is used; its
+// neglected part is below 1e-20 relative there for m <= kMaxL.
+constexpr double kBoysH = 1.0 / 32.0;
+constexpr double kBoysInvH = 32.0;
+constexpr int kBoysJ = 7;
+constexpr double kBoysTMax = 120.0;
+constexpr int kBoysRows = 120 * 32 + 2;
+constexpr int kBoysCols = kMaxL + kBoysJ + 2;  // 37
+// Row kBoysRows of the uploaded table holds the asymptotic coefficients
+// (2m-1)!! sqrt(pi) / 2^(m+1) = Gamma(m+1/2)/2, so F_m(T) = c_m / (T^m sqrt(T)).
+constexpr int kBoysAsymRow = kBoysRows;
+
+// Pyramidal number: Hermite functions with total order <= n.
+__host__ __device__ constexpr int nherm(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// Hermite recursion tables: for each L in 0..kMaxL, the nherm(L) triples
+// (t,u,v) with t+u+v <= L ordered by total order, each packed as
+//   bits 0..15  offset t*(L+1)^2 + u*(L+1) + v in the (L+1)^3 box,
+//   bits 16..17 the axis raised by eq. (md1) to reach it (0 x, 1 y, 2 z;
+//               the last non-zero of t, u, v),
+//   bits 18..23 the index along that axis.
+// rtab_start[L] is the first entry of table L.
+constexpr int kRtabTotal = 35960;  // sum_{L=0}^{28} nherm(L)
+
+// One workgroup computes a tile of kRowBlocks*16 bra rows (ab) of one quartet.
+constexpr int kWaves = 8;
+constexpr int kThreads = kWaves * 64;
+constexpr int kBoxLMax = 24;  // largest L whose (L+1)^3 box fits in LDS
+constexpr int kRPerThread = (nherm(kBoxLMax) + kThreads - 1) / kThreads;  // 6
+
+// Everything the fused kernel needs to know about one class (la lb|lc ld).
+struct ClassParams {
+  int la, lb, lc, ld;
+  int na, nb, nc, nd;
+  int nab, ncd;
+  int Lb, Lk, L;
+  int np, nq;      // Hermite functions of the bra and the ket
+  int np4, nq4;    // padded to a multiple of 4 (MFMA K step)
+  int nqb;         // 16-wide column blocks of [ab|q]
+  int ncdb;        // 16-wide column blocks of (ab|cd)
+  int nrt;         // row tiles per quartet
+  int S1, S2;      // strides of the (L+1)^3 box: u -> S1, t -> S2
+  int tbrow, tkrow;    // 1-d E table row lengths (Lb+2, Lk+2); last entry is 0
+  int tbaxis, tkaxis;  // doubles per axis of the bra / ket tables (incl. zero row)
+  int xs;              // row stride (doubles) of the [ab|q] tile in LDS
+  int kmax;
+  // LDS layout (byte offsets)
+  int o_union;   // phase 1: R box then bra tables; phase 2: [ab|q] tile then ket tables
+  int o_brae;    // bra tables (phase 1)
+  int o_kete;    // ket tables (phase 2)
+  int o_ptab, o_qtab, o_base, o_shell;
+  int lds_bytes;
+};
+
+}  // namespace eri4

@@ -1,0 +1,151 @@
+"""Thin Python binding of liberi4.so (the gfx950 HIP library).
+
+Argument marshalling only: every step of the computation runs in the library's
+kernels.  Device buffers are torch tensors on the current ROCm device; the
+stream is torch's current stream unless one is given.  The functions mirror
+the C entry points declared in include/eri4.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liberi4.so")
+
+ERI4_MAX_L = 6
+ERI4_MAX_K = 16
+ERI4_MAX_BOYS_M = 28
+
+STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UNSUPPORTED",
+          3: "ERI4_ERROR_OUT_OF_MEMORY", 4: "ERI4_ERROR_HIP", 5: "ERI4_ERROR_INTERNAL"}
+
+# every symbol include/eri4.h declares
+EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version", "eri4_init",
+           "eri4_batch", "eri4_boys", "eri4_hermite_r", "eri4_hermite_e")
+
+_lib = None
+
+
+class Eri4Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load liberi4.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_03452_amd.build` "
+                               "(or __graft_entry__.build()); there is no non-HIP fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.eri4_ncart.argtypes = [c_int]
+        L.eri4_ncart.restype = c_int
+        L.eri4_quartet_size.argtypes = [c_int] * 4
+        L.eri4_quartet_size.restype = i64
+        L.eri4_last_error.restype = ctypes.c_char_p
+        L.eri4_version.restype = ctypes.c_char_p
+        L.eri4_init.restype = c_int
+        L.eri4_batch.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp]
+        L.eri4_batch.restype = c_int
+        L.eri4_boys.argtypes = [c_int, i64, vp, vp, vp]
+        L.eri4_boys.restype = c_int
+        L.eri4_hermite_r.argtypes = [c_int, i64, vp, vp, vp, vp, vp, vp]
+        L.eri4_hermite_r.restype = c_int
+        L.eri4_hermite_e.argtypes = [c_int, c_int, i64, vp, vp, vp, vp, vp, vp]
+        L.eri4_hermite_e.restype = c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise Eri4Error(st, lib().eri4_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype_name: str):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensors expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensors expected")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise ValueError(f"{dtype_name} tensor expected, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def ncart(l: int) -> int:
+    return lib().eri4_ncart(int(l))
+
+
+def quartet_size(la, lb, lc, ld) -> int:
+    return lib().eri4_quartet_size(int(la), int(lb), int(lc), int(ld))
+
+
+def version() -> str:
+    return lib().eri4_version().decode()
+
+
+def init():
+    _check(lib().eri4_init())
+
+
+def batch(ls, centers, exps, coefs, nprim, out=None, stream=None):
+    """(ab|cd) for one class ls = (la, lb, lc, ld).
+
+    centers float64 [nq,4,3], exps/coefs float64 [nq,4,kmax], nprim int32 [nq,4]
+    (all device tensors); returns out float64 [nq, Na, Nb, Nc, Nd].
+    """
+    import torch
+    la, lb, lc, ld = (int(x) for x in ls)
+    nq = centers.shape[0]
+    kmax = exps.shape[2]
+    if out is None:
+        out = torch.empty((nq, ncart(la), ncart(lb), ncart(lc), ncart(ld)), dtype=torch.float64,
+                          device=centers.device)
+    _check(lib().eri4_batch(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
+                            _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(out, "float64"),
+                            _stream(stream)))
+    return out
+
+
+def boys(mmax, T, F=None, stream=None):
+    import torch
+    n = T.shape[0]
+    if F is None:
+        F = torch.empty((n, mmax + 1), dtype=torch.float64, device=T.device)
+    _check(lib().eri4_boys(int(mmax), n, _ptr(T, "float64"), _ptr(F, "float64"), _stream(stream)))
+    return F
+
+
+def hermite_r(L, zp, zq, P, Q, R=None, stream=None):
+    import torch
+    n = zp.shape[0]
+    if R is None:
+        R = torch.empty((n, L + 1, L + 1, L + 1), dtype=torch.float64, device=zp.device)
+    _check(lib().eri4_hermite_r(int(L), n, _ptr(zp, "float64"), _ptr(zq, "float64"), _ptr(P, "float64"),
+                                _ptr(Q, "float64"), _ptr(R, "float64"), _stream(stream)))
+    return R
+
+
+def hermite_e(la, lb, za, zb, A, B, E=None, stream=None):
+    import torch
+    n = za.shape[0]
+    if E is None:
+        E = torch.empty((n, 3, la + 1, lb + 1, la + lb + 1), dtype=torch.float64, device=za.device)
+    _check(lib().eri4_hermite_e(int(la), int(lb), n, _ptr(za, "float64"), _ptr(zb, "float64"),
+                                _ptr(A, "float64"), _ptr(B, "float64"), _ptr(E, "float64"), _stream(stream)))
+    return E

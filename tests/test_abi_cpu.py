@@ -1,0 +1,88 @@
+"""The C ABI library loads, exports what include/eri4.h declares, and rejects
+bad arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2307_03452_amd import eri4
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eri4.h")
+STATUS_INVALID, STATUS_UNSUPPORTED = 1, 2
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eri4_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = eri4.lib()
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(eri4.EXPORTS) == names
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    for name in ("ERI4_MAX_L", "ERI4_MAX_K", "ERI4_MAX_BOYS_M"):
+        v = int(re.search(r"#define\s+%s\s+(\d+)" % name, text).group(1))
+        assert v == getattr(eri4, name)
+
+
+def test_sizes():
+    assert [eri4.ncart(l) for l in range(8)] == [1, 3, 6, 10, 15, 21, 28, 36]
+    assert eri4.ncart(-1) == -1
+    assert eri4.quartet_size(6, 6, 6, 6) == 28 ** 4
+    assert eri4.quartet_size(4, 5, 6, 0) == 15 * 21 * 28
+    assert eri4.quartet_size(-1, 0, 0, 0) == -1
+    assert "gfx950" in eri4.version()
+
+
+def _batch(la, lb, lc, ld, nq, kmax, ptr=1):
+    p = ctypes.c_void_p(ptr) if ptr else None
+    return eri4.lib().eri4_batch(la, lb, lc, ld, nq, p, p, p, p, kmax, p, None)
+
+
+def test_batch_rejects_bad_arguments_on_host():
+    L = eri4.lib()
+    assert _batch(-1, 0, 0, 0, 1, 1) == STATUS_INVALID
+    assert b"angular" in L.eri4_last_error()
+    assert _batch(7, 0, 0, 0, 1, 1) == STATUS_UNSUPPORTED
+    assert _batch(0, 0, 0, 0, -1, 1) == STATUS_INVALID
+    assert _batch(0, 0, 0, 0, 1, 0) == STATUS_INVALID
+    assert _batch(0, 0, 0, 0, 1, 17) == STATUS_INVALID
+    assert _batch(4, 4, 4, 4, 5, 1, ptr=0) == STATUS_INVALID
+    assert b"NULL" in L.eri4_last_error()
+    # nothing to do: success without touching the device or the pointers
+    assert _batch(4, 4, 4, 4, 0, 1, ptr=0) == 0
+
+
+def test_stage_entry_points_reject_bad_arguments_on_host():
+    L = eri4.lib()
+    n = ctypes.c_void_p(None)
+    assert L.eri4_boys(-1, 1, n, n, None) == STATUS_INVALID
+    assert L.eri4_boys(29, 1, n, n, None) == STATUS_INVALID
+    assert L.eri4_boys(4, 3, n, n, None) == STATUS_INVALID
+    assert L.eri4_boys(4, 0, n, n, None) == 0
+    assert L.eri4_hermite_r(25, 1, n, n, n, n, n, None) == STATUS_INVALID
+    assert L.eri4_hermite_r(4, 1, n, n, n, n, n, None) == STATUS_INVALID
+    assert L.eri4_hermite_e(8, 0, 1, n, n, n, n, n, None) == STATUS_INVALID
+    assert L.eri4_hermite_e(2, 2, -1, n, n, n, n, n, None) == STATUS_INVALID
+
+
+def test_errors_are_per_thread():
+    import threading
+    L = eri4.lib()
+    assert _batch(-1, 0, 0, 0, 1, 1) == STATUS_INVALID
+    seen = []
+    t = threading.Thread(target=lambda: seen.append(L.eri4_last_error()))
+    t.start()
+    t.join()
+    assert seen == [b""]
+    assert L.eri4_last_error() != b""
