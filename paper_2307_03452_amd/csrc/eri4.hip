@@ -211,6 +211,112 @@ __device__ __forceinline__ void make_pair(double* out, double za, double zb, dou
   out[1] = ca * cb * exp(-za * zb * iz * ab2);
 }
 
+// First transform over one bra primitive pair, NR row blocks x NC column
+// blocks of this wave (both wave-uniform):
+//   acc[r][c] += sum_p E_ab[row block r][p] * box[off(p) + off(q in block c)]
+// All LDS reads of a k step are issued before its MFMAs; the next p index is
+// fetched one step ahead.
+template <int NR, int NC, int RB, int C1>
+__device__ __forceinline__ void gemm1_run(d4 (&acc)[RB][C1], const double* __restrict__ brae,
+                                          const double* __restrict__ box, const int2* __restrict__ ptab,
+                                          const int (&rowx)[RB], const int (&rowy)[RB], const int (&rowz)[RB],
+                                          const int (&offq)[C1], int np4, int lane) {
+  const int g = lane >> 4;
+  int2 pt = ptab[g];
+  for (int kk = 0; kk < np4; kk += 4) {
+    const int tp = pt.x & 0xff, up = (pt.x >> 8) & 0xff, vp = pt.x >> 16;
+    double ex[NR], ey[NR], ez[NR], b[NC];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      ex[r] = brae[rowx[r] + tp];
+      ey[r] = brae[rowy[r] + up];
+      ez[r] = brae[rowz[r] + vp];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) b[c] = box[pt.y + offq[c]];
+    pt = ptab[min(kk + 4, np4 - 4) + g];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double a = ex[r] * ey[r] * ez[r];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[r][c] = mfma16(a, b[c], acc[r][c]);
+    }
+  }
+}
+
+template <int RB, int C1>
+__device__ __forceinline__ void gemm1(int nr, int nc, d4 (&acc)[RB][C1], const double* brae, const double* box,
+                                      const int2* ptab, const int (&rowx)[RB], const int (&rowy)[RB],
+                                      const int (&rowz)[RB], const int (&offq)[C1], int np4, int lane) {
+#define G1(NR, NC) \
+  if (nr == NR && nc == NC) { gemm1_run<NR, NC>(acc, brae, box, ptab, rowx, rowy, rowz, offq, np4, lane); return; }
+  if constexpr (RB >= 1) {
+    if constexpr (C1 >= 1) G1(1, 1)
+    if constexpr (C1 >= 2) G1(1, 2)
+    if constexpr (C1 >= 3) G1(1, 3)
+    if constexpr (C1 >= 4) G1(1, 4)
+  }
+  if constexpr (RB >= 2) {
+    if constexpr (C1 >= 1) G1(2, 1)
+    if constexpr (C1 >= 2) G1(2, 2)
+    if constexpr (C1 >= 3) G1(2, 3)
+    if constexpr (C1 >= 4) G1(2, 4)
+  }
+#undef G1
+}
+
+// Second transform for a group of NC column blocks of this wave:
+//   acc[r][c] = sum_q X[row block r][q] * E_cd[col block c][q]
+// with E_cd the product of three ket table entries (sign of eq. (pq) folded in).
+template <int NR, int NC, int RB, int CG>
+__device__ __forceinline__ void gemm2_run(d4 (&acc)[RB][CG], const double* __restrict__ X, int xs,
+                                          const double* __restrict__ kete, const int2* __restrict__ qtab,
+                                          const int (&kx)[CG], const int (&ky)[CG], const int (&kz)[CG], int nq4,
+                                          int lane) {
+  const int g = lane >> 4, n = lane & 15;
+  int pk = qtab[g].x;
+  for (int kk = 0; kk < nq4; kk += 4) {
+    const int tq = pk & 0xff, uq = (pk >> 8) & 0xff, vq = pk >> 16;
+    double a[NR], fx[NC], fy[NC], fz[NC];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a[r] = X[(r * 16 + n) * xs + kk + g];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      fx[c] = kete[kx[c] + tq];
+      fy[c] = kete[ky[c] + uq];
+      fz[c] = kete[kz[c] + vq];
+    }
+    pk = qtab[min(kk + 4, nq4 - 4) + g].x;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double b = fx[c] * fy[c] * fz[c];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r][c] = mfma16(a[r], b, acc[r][c]);
+    }
+  }
+}
+
+template <int RB, int CG>
+__device__ __forceinline__ void gemm2(int nr, int nc, d4 (&acc)[RB][CG], const double* X, int xs,
+                                      const double* kete, const int2* qtab, const int (&kx)[CG],
+                                      const int (&ky)[CG], const int (&kz)[CG], int nq4, int lane) {
+#define G2(NR, NC) \
+  if (nr == NR && nc == NC) { gemm2_run<NR, NC>(acc, X, xs, kete, qtab, kx, ky, kz, nq4, lane); return; }
+  if constexpr (RB >= 1) {
+    if constexpr (CG >= 1) G2(1, 1)
+    if constexpr (CG >= 2) G2(1, 2)
+    if constexpr (CG >= 3) G2(1, 3)
+    if constexpr (CG >= 4) G2(1, 4)
+  }
+  if constexpr (RB >= 2) {
+    if constexpr (CG >= 1) G2(2, 1)
+    if constexpr (CG >= 2) G2(2, 2)
+    if constexpr (CG >= 3) G2(2, 3)
+    if constexpr (CG >= 4) G2(2, 4)
+  }
+#undef G2
+}
+
 template <int RB, int C1, int C2G>
 __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
     const ClassParams cp, const double* __restrict__ boys_tab, const uint32_t* __restrict__ rtab_L,
@@ -218,7 +324,8 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
     const double* __restrict__ coefs, const int32_t* __restrict__ nprim, double* __restrict__ out,
     int64_t q0) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
   const int64_t q = q0 + blockIdx.x / cp.nrt;
   const int rt = blockIdx.x % cp.nrt;
   const int kmax = cp.kmax;
@@ -291,6 +398,8 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
     offq[c] = (cb < cp.nqb) ? qtab[cb * 16 + (lane & 15)].y : 0;
   }
   const int ncbw = (wave < cp.ncdb) ? (cp.ncdb - wave + 7) / 8 : 0;  // output column blocks of this wave
+  const int nc1 = (wave < cp.nqb) ? min(C1, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
+  const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                        // valid row blocks of this tile
 
   const double pref = 2.0 * pow(M_PI, 2.5);
   const int64_t qoff = q * (int64_t)cp.nab * cp.ncd;
@@ -339,22 +448,7 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
       hermite_r_box(box, baseM, cp.L, cp.S1, cp.S2, pqv, rtab_L, tid);
 
       // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
-      for (int kk = 0; kk < cp.np4; kk += 4) {
-        const int2 pt = ptab[kk + (lane >> 4)];
-        const int tp = pt.x & 0xff, up = (pt.x >> 8) & 0xff, vp = pt.x >> 16;
-        double a[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) a[r] = brae[rowx[r] + tp] * brae[rowy[r] + up] * brae[rowz[r] + vp];
-#pragma unroll
-        for (int c = 0; c < C1; ++c) {
-          if (wave + 8 * c < cp.nqb) {
-            const double b = box[pt.y + offq[c]];
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-              if (rbv[r]) acc1[r][c] = mfma16(a[r], b, acc1[r][c]);
-          }
-        }
-      }
+      if (nc1 > 0) gemm1<RB, C1>(nrv, nc1, acc1, brae, box, ptab, rowx, rowy, rowz, offq, cp.np4, lane);
       __syncthreads();
     }
 
@@ -402,23 +496,7 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
       for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int c = 0; c < C2G; ++c) acc2[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
-      for (int kk = 0; kk < cp.nq4; kk += 4) {
-        const int qq = kk + (lane >> 4);
-        const int pk = qtab[qq].x;
-        const int tq = pk & 0xff, uq = (pk >> 8) & 0xff, vq = pk >> 16;
-        double a[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) a[r] = X[(r * 16 + (lane & 15)) * cp.xs + qq];
-#pragma unroll
-        for (int c = 0; c < C2G; ++c) {
-          if (cv[c]) {
-            const double b = kete[kx[c] + tq] * kete[ky[c] + uq] * kete[kz[c] + vq];
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-              if (rbv[r]) acc2[r][c] = mfma16(a[r], b, acc2[r][c]);
-          }
-        }
-      }
+      gemm2<RB, C2G>(nrv, min(C2G, ncbw - g0), acc2, X, cp.xs, kete, qtab, kx, ky, kz, cp.nq4, lane);
 #pragma unroll
       for (int r = 0; r < RB; ++r)
 #pragma unroll
