@@ -143,33 +143,38 @@ __device__ __forceinline__ void cart_of(int l, int i, int& x, int& y, int& z) {
 // [r]^(0) for |r| <= L in the (L+1)^3 LDS box, by eq. (md1) for decreasing m,
 // overwriting [r]^(m+1) with [r]^(m).  Each level is computed into registers
 // (up to kRPerThread entries per thread), then written after a barrier.
-// baseM[m] holds [0]^(m); PQ (3 doubles, LDS) is P - Q.  The recursion table
-// rt is re-read every level so that its decoded form is not kept live.
+// baseM[m] holds [0]^(m); PQ (3 doubles, LDS) is P - Q.  ent[] holds this
+// thread's packed recursion-table entries; they are made opaque every level so
+// that only the 32-bit entries stay live, not their decoded form.
 __device__ void hermite_r_box(double* box, const double* baseM, int L, int S1, int S2,
-                              const double* PQ, const uint32_t* __restrict__ rt, int tid) {
+                              const double* PQ, const uint32_t (&ent_in)[kRPerThread], int tid) {
+  uint32_t ent[kRPerThread];
+#pragma unroll
+  for (int k = 0; k < kRPerThread; ++k) ent[k] = ent_in[k];
   if (tid == 0) box[0] = baseM[L];
   __syncthreads();
+  const double px = PQ[0], py = PQ[1], pz = PQ[2];
   for (int m = L - 1; m >= 0; --m) {
     const int nact = nherm(L - m);
-    const uint32_t* rtm = rt;
-    asm volatile("" : "+s"(rtm));  // opaque: reload the entries every level
     double nv[kRPerThread];
 #pragma unroll
     for (int k = 0; k < kRPerThread; ++k) {
+      asm volatile("" : "+v"(ent[k]));
       const int e = tid + k * kThreads;
       nv[k] = 0.0;
       if (e < nact) {
         if (e == 0) {
           nv[k] = baseM[m];
         } else {
-          const uint32_t w = rtm[e];
+          const uint32_t w = ent[k];
           const int tgt = (int)(w & 0xffffu);
           const int dir = (int)((w >> 16) & 3u);
           const int ri = (int)((w >> 18) & 63u);
           const int stride = dir == 0 ? S2 : (dir == 1 ? S1 : 1);
+          const double pq = dir == 0 ? px : (dir == 1 ? py : pz);
           const int o1 = tgt - stride;
           const int o2 = ri >= 2 ? o1 - stride : o1;
-          nv[k] = PQ[dir] * box[o1] + (double)(ri - 1) * box[o2];
+          nv[k] = pq * box[o1] + (double)(ri - 1) * box[o2];
         }
       }
     }
@@ -177,15 +182,21 @@ __device__ void hermite_r_box(double* box, const double* baseM, int L, int S1, i
 #pragma unroll
     for (int k = 0; k < kRPerThread; ++k) {
       const int e = tid + k * kThreads;
-      if (e < nact) box[rtm[e] & 0xffffu] = nv[k];
+      if (e < nact) box[ent[k] & 0xffffu] = nv[k];
     }
     __syncthreads();
   }
 }
 
-// ---------------------------------------------------------------------------
-// fused kernel
-// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_rtab(uint32_t (&ent)[kRPerThread], const uint32_t* __restrict__ rt,
+                                          int L, int tid) {
+  const int n = nherm(L);
+#pragma unroll
+  for (int k = 0; k < kRPerThread; ++k) {
+    const int e = tid + k * kThreads;
+    ent[k] = (e < n) ? rt[e] : 0u;
+  }
+}
 
 // Primitive-pair data, stored in LDS as 11 doubles:
 //   [0] z = za + zb, [1] w = ca cb exp(-za zb / z |A-B|^2) (Gaussian product
@@ -211,16 +222,16 @@ __device__ __forceinline__ void make_pair(double* out, double za, double zb, dou
   out[1] = ca * cb * exp(-za * zb * iz * ab2);
 }
 
-// First transform over one bra primitive pair, NR row blocks x NC column
-// blocks of this wave (both wave-uniform):
+// First transform over one bra primitive pair for NR row blocks x NC column
+// blocks of this wave (both fixed per wave):
 //   acc[r][c] += sum_p E_ab[row block r][p] * box[off(p) + off(q in block c)]
-// All LDS reads of a k step are issued before its MFMAs; the next p index is
-// fetched one step ahead.
-template <int NR, int NC, int RB, int C1>
-__device__ __forceinline__ void gemm1_run(d4 (&acc)[RB][C1], const double* __restrict__ brae,
-                                          const double* __restrict__ box, const int2* __restrict__ ptab,
-                                          const int (&rowx)[RB], const int (&rowy)[RB], const int (&rowz)[RB],
-                                          const int (&offq)[C1], int np4, int lane) {
+// E_ab is the product of three bra-table entries.  All LDS reads of a k step
+// are issued before its MFMAs; the next p index is fetched one step ahead.
+template <int NR, int NC>
+__device__ __forceinline__ void gemm1_pair(d4 (&acc)[NR][NC], const double* __restrict__ brae,
+                                           const double* __restrict__ box, const int2* __restrict__ ptab,
+                                           const int (&rowx)[NR], const int (&rowy)[NR], const int (&rowz)[NR],
+                                           const int (&offq)[NC], int np4, int lane) {
   const int g = lane >> 4;
   int2 pt = ptab[g];
   for (int kk = 0; kk < np4; kk += 4) {
@@ -244,36 +255,40 @@ __device__ __forceinline__ void gemm1_run(d4 (&acc)[RB][C1], const double* __res
   }
 }
 
-template <int RB, int C1>
-__device__ __forceinline__ void gemm1(int nr, int nc, d4 (&acc)[RB][C1], const double* brae, const double* box,
-                                      const int2* ptab, const int (&rowx)[RB], const int (&rowy)[RB],
-                                      const int (&rowz)[RB], const int (&offq)[C1], int np4, int lane) {
-#define G1(NR, NC) \
-  if (nr == NR && nc == NC) { gemm1_run<NR, NC>(acc, brae, box, ptab, rowx, rowy, rowz, offq, np4, lane); return; }
-  if constexpr (RB >= 1) {
-    if constexpr (C1 >= 1) G1(1, 1)
-    if constexpr (C1 >= 2) G1(1, 2)
-    if constexpr (C1 >= 3) G1(1, 3)
-    if constexpr (C1 >= 4) G1(1, 4)
-  }
-  if constexpr (RB >= 2) {
-    if constexpr (C1 >= 1) G1(2, 1)
-    if constexpr (C1 >= 2) G1(2, 2)
-    if constexpr (C1 >= 3) G1(2, 3)
-    if constexpr (C1 >= 4) G1(2, 4)
-  }
-#undef G1
-}
-
-// Second transform for a group of NC column blocks of this wave:
-//   acc[r][c] = sum_q X[row block r][q] * E_cd[col block c][q]
-// with E_cd the product of three ket table entries (sign of eq. (pq) folded in).
-template <int NR, int NC, int RB, int CG>
-__device__ __forceinline__ void gemm2_run(d4 (&acc)[RB][CG], const double* __restrict__ X, int xs,
-                                          const double* __restrict__ kete, const int2* __restrict__ qtab,
-                                          const int (&kx)[CG], const int (&ky)[CG], const int (&kz)[CG], int nq4,
-                                          int lane) {
+// Second transform for one group of NC output column blocks (cb0, cb0+8, ...)
+// and NR row blocks, then the output write:
+//   out[ab][cd] (+)= sum_q X[ab][q] E_cd[cd][q]
+// E_cd is the product of three ket-table entries (sign of eq. (pq) folded in).
+template <int NR, int NC>
+__device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double* __restrict__ X,
+                                            const double* __restrict__ kete, const int2* __restrict__ qtab,
+                                            int cb0, int row0, double* __restrict__ outq, bool first, int lane) {
   const int g = lane >> 4, n = lane & 15;
+  int kx[NC], ky[NC], kz[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int cd = (cb0 + 8 * c) * 16 + n;
+    if (cd < cp.ncd) {
+      const int ic = cd / cp.nd, id = cd - (cd / cp.nd) * cp.nd;
+      int cx, cy, cz, dx, dy, dz;
+      cart_of(cp.lc, ic, cx, cy, cz);
+      cart_of(cp.ld, id, dx, dy, dz);
+      kx[c] = (cx * (cp.ld + 1) + dx) * cp.tkrow;
+      ky[c] = cp.tkaxis + (cy * (cp.ld + 1) + dy) * cp.tkrow;
+      kz[c] = 2 * cp.tkaxis + (cz * (cp.ld + 1) + dz) * cp.tkrow;
+    } else {
+      const int zr = (cp.lc + 1) * (cp.ld + 1) * cp.tkrow;
+      kx[c] = zr;
+      ky[c] = cp.tkaxis + zr;
+      kz[c] = 2 * cp.tkaxis + zr;
+    }
+  }
+  d4 acc[NR][NC];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
+  const int xs = cp.xs, nq4 = cp.nq4;
   int pk = qtab[g].x;
   for (int kk = 0; kk < nq4; kk += 4) {
     const int tq = pk & 0xff, uq = (pk >> 8) & 0xff, vq = pk >> 16;
@@ -294,86 +309,52 @@ __device__ __forceinline__ void gemm2_run(d4 (&acc)[RB][CG], const double* __res
       for (int r = 0; r < NR; ++r) acc[r][c] = mfma16(a[r], b, acc[r][c]);
     }
   }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int cd = (cb0 + 8 * c) * 16 + n;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int ab = row0 + r * 16 + 4 * jj + g;
+        if (ab < cp.nab && cd < cp.ncd) {
+          double* o = outq + (int64_t)ab * cp.ncd + cd;
+          if (first)
+            __builtin_nontemporal_store(acc[r][c][jj], o);
+          else
+            *o += acc[r][c][jj];
+        }
+      }
+    }
 }
 
-template <int RB, int CG>
-__device__ __forceinline__ void gemm2(int nr, int nc, d4 (&acc)[RB][CG], const double* X, int xs,
-                                      const double* kete, const int2* qtab, const int (&kx)[CG],
-                                      const int (&ky)[CG], const int (&kz)[CG], int nq4, int lane) {
-#define G2(NR, NC) \
-  if (nr == NR && nc == NC) { gemm2_run<NR, NC>(acc, X, xs, kete, qtab, kx, ky, kz, nq4, lane); return; }
-  if constexpr (RB >= 1) {
-    if constexpr (CG >= 1) G2(1, 1)
-    if constexpr (CG >= 2) G2(1, 2)
-    if constexpr (CG >= 3) G2(1, 3)
-    if constexpr (CG >= 4) G2(1, 4)
-  }
-  if constexpr (RB >= 2) {
-    if constexpr (CG >= 1) G2(2, 1)
-    if constexpr (CG >= 2) G2(2, 2)
-    if constexpr (CG >= 3) G2(2, 3)
-    if constexpr (CG >= 4) G2(2, 4)
-  }
-#undef G2
-}
+// LDS regions of the fused kernel (see make_params for the layout).
+struct Lds {
+  double *sh, *baseM, *kpair, *bpair, *pqv, *box, *brae, *X, *kete;
+  int2 *ptab, *qtab;
+};
 
-template <int RB, int C1, int C2G>
-__global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
-    const ClassParams cp, const double* __restrict__ boys_tab, const uint32_t* __restrict__ rtab_L,
-    const double* __restrict__ centers, const double* __restrict__ exps,
-    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, double* __restrict__ out,
-    int64_t q0) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
-  const int64_t q = q0 + blockIdx.x / cp.nrt;
-  const int rt = blockIdx.x % cp.nrt;
+constexpr int kGroup = 4;  // output column blocks per second-transform pass
+
+// Everything a workgroup does after its prologue, for NR valid row blocks and
+// NC1 first-transform column blocks of this wave.
+template <int NR, int NC1>
+__device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, const double* __restrict__ boys_tab,
+                           const uint32_t (&rent)[kRPerThread], double* __restrict__ out, int64_t q, int rt,
+                           int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane) {
   const int kmax = cp.kmax;
-
-  double* sh = (double*)(lds + cp.o_shell);
-  int* shn = (int*)(sh + 12 + 8 * kmax);
-  double* baseM = (double*)(lds + cp.o_base);
-  int2* ptab = (int2*)(lds + cp.o_ptab);
-  int2* qtab = (int2*)(lds + cp.o_qtab);
-  double* box = (double*)(lds + cp.o_union);
-  double* brae = (double*)(lds + cp.o_brae);
-  double* X = (double*)(lds + cp.o_union);
-  double* kete = (double*)(lds + cp.o_kete);
-
-  // shell data of this quartet
-  if (tid < 12) {
-    sh[tid] = centers[q * 12 + tid];
-  } else if (tid < 12 + 8 * kmax) {
-    const int j = tid - 12;
-    sh[tid] = (j < 4 * kmax) ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)];
-  } else if (tid >= 256 && tid < 260) {
-    shn[tid - 256] = nprim[q * 4 + (tid - 256)];
-  }
-  build_htab(ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, tid);
-  build_htab(qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, tid);
-  __syncthreads();
-
-  const int Ka = shn[0], Kb = shn[1], Kc = shn[2], Kd = shn[3];
-  const int row0 = rt * RB * 16;
-  if (Ka < 1 || Ka > kmax || Kb < 1 || Kb > kmax || Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax) {
-    const int nrows = min(RB * 16, cp.nab - row0);
-    double* o = out + q * (int64_t)cp.nab * cp.ncd + (int64_t)row0 * cp.ncd;
-    for (int i = tid; i < nrows * cp.ncd; i += kThreads) o[i] = __builtin_nan("");
-    return;
-  }
-  const double* A = sh;
-  const double* B = sh + 3;
-  const double* C = sh + 6;
-  const double* D = sh + 9;
-  const double* ex = sh + 12;
-  const double* co = sh + 12 + 4 * kmax;
+  const double* A = s.sh;
+  const double* B = s.sh + 3;
+  const double* C = s.sh + 6;
+  const double* D = s.sh + 9;
+  const double* ex = s.sh + 12;
+  const double* co = s.sh + 12 + 4 * kmax;
+  constexpr int NC1A = NC1 > 0 ? NC1 : 1;
 
   // bra rows of this lane (A operand of the first transform)
-  int rowx[RB], rowy[RB], rowz[RB];
-  bool rbv[RB];
+  int rowx[NR], rowy[NR], rowz[NR];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    rbv[r] = row0 + r * 16 < cp.nab;
+  for (int r = 0; r < NR; ++r) {
     const int ab = row0 + r * 16 + (lane & 15);
     if (ab < cp.nab) {
       const int ia = ab / cp.nb, ib = ab - ia * cp.nb;
@@ -391,133 +372,167 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
     }
   }
   // [ab|q] columns of this lane (B operand of the first transform)
-  int offq[C1];
+  int offq[NC1A];
 #pragma unroll
-  for (int c = 0; c < C1; ++c) {
-    const int cb = wave + 8 * c;
-    offq[c] = (cb < cp.nqb) ? qtab[cb * 16 + (lane & 15)].y : 0;
-  }
+  for (int c = 0; c < NC1A; ++c) offq[c] = (c < NC1) ? s.qtab[(wave + 8 * c) * 16 + (lane & 15)].y : 0;
   const int ncbw = (wave < cp.ncdb) ? (cp.ncdb - wave + 7) / 8 : 0;  // output column blocks of this wave
-  const int nc1 = (wave < cp.nqb) ? min(C1, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
-  const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                        // valid row blocks of this tile
 
   const double pref = 2.0 * pow(M_PI, 2.5);
-  const int64_t qoff = q * (int64_t)cp.nab * cp.ncd;
-  double* kpair = baseM + 32;
-  double* bpair = kpair + 16;
-  double* pqv = bpair + 16;
+  double* outq = out + q * (int64_t)cp.nab * cp.ncd;
 
   for (int kl = 0; kl < Kc * Kd; ++kl) {
     if (tid == 0) {
       const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
-      make_pair(kpair, ex[2 * kmax + k], ex[3 * kmax + l], co[2 * kmax + k], co[3 * kmax + l], C, D);
+      make_pair(s.kpair, ex[2 * kmax + k], ex[3 * kmax + l], co[2 * kmax + k], co[3 * kmax + l], C, D);
     }
-    d4 acc1[RB][C1];
+    d4 acc1[NR][NC1A];
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int c = 0; c < C1; ++c) acc1[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
+      for (int c = 0; c < NC1A; ++c) acc1[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
 
     for (int ij = 0; ij < Ka * Kb; ++ij) {
       if (tid == 64) {
         const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
-        make_pair(bpair, ex[i], ex[kmax + j], co[i], co[kmax + j], A, B);
+        make_pair(s.bpair, ex[i], ex[kmax + j], co[i], co[kmax + j], A, B);
       }
       __syncthreads();
       if (wave == 0) {
-        if (lane < 3) pqv[lane] = bpair[2 + lane] - kpair[2 + lane];
+        if (lane < 3) s.pqv[lane] = s.bpair[2 + lane] - s.kpair[2 + lane];
         if (lane <= cp.L) {
-          const double zp = bpair[0], zq = kpair[0];
+          const double zp = s.bpair[0], zq = s.kpair[0];
           const double zs = zp + zq;
           const double rho = zp * zq / zs;
           double r2 = 0.0;
 #pragma unroll
           for (int x = 0; x < 3; ++x) {
-            const double d = bpair[2 + x] - kpair[2 + x];
+            const double d = s.bpair[2 + x] - s.kpair[2 + x];
             r2 += d * d;
           }
           const double F = boys_fm(lane, rho * r2, boys_tab);
           double pw = 1.0;
           for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
-          baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (bpair[1] * kpair[1]) * F;
+          s.baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (s.bpair[1] * s.kpair[1]) * F;
         }
       } else if (wave == 1) {
-        build_etab(brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / bpair[0], bpair + 5, bpair + 8, false, lane);
+        build_etab(s.brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / s.bpair[0], s.bpair + 5, s.bpair + 8, false,
+                   lane);
       }
       __syncthreads();
-      hermite_r_box(box, baseM, cp.L, cp.S1, cp.S2, pqv, rtab_L, tid);
-
+      hermite_r_box(s.box, s.baseM, cp.L, cp.S1, cp.S2, s.pqv, rent, tid);
       // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
-      if (nc1 > 0) gemm1<RB, C1>(nrv, nc1, acc1, brae, box, ptab, rowx, rowy, rowz, offq, cp.np4, lane);
+      if constexpr (NC1 > 0) gemm1_pair<NR, NC1>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, cp.np4, lane);
       __syncthreads();
     }
 
-    // [ab_tile|q] -> LDS (aliases the R box), ket tables for kl
+    // [ab_tile|q] -> LDS (aliases the R box); ket tables for kl
+    if constexpr (NC1 > 0) {
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+      for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int c = 0; c < C1; ++c) {
-        const int cb = wave + 8 * c;
-        if (cb < cp.nqb && rbv[r]) {
+        for (int c = 0; c < NC1; ++c) {
+          const int cb = wave + 8 * c;
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj)
-            X[(r * 16 + 4 * jj + (lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = acc1[r][c][jj];
+            s.X[(r * 16 + 4 * jj + (lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = acc1[r][c][jj];
         }
-      }
+    }
     if (wave == 0)
-      build_etab(kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / kpair[0], kpair + 5, kpair + 8, true, lane);
+      build_etab(s.kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / s.kpair[0], s.kpair + 5, s.kpair + 8, true, lane);
     __syncthreads();
 
-    // second transform: (ab|cd) += sum_q E_cd^q [ab|q], written to HBM
-    for (int g0 = 0; g0 < ncbw; g0 += C2G) {
-      int kx[C2G], ky[C2G], kz[C2G];
-      bool cv[C2G];
-#pragma unroll
-      for (int c = 0; c < C2G; ++c) {
-        cv[c] = g0 + c < ncbw;
-        const int cd = (wave + 8 * (g0 + c)) * 16 + (lane & 15);
-        if (cv[c] && cd < cp.ncd) {
-          const int ic = cd / cp.nd, id = cd - (cd / cp.nd) * cp.nd;
-          int cx, cy, cz, dx, dy, dz;
-          cart_of(cp.lc, ic, cx, cy, cz);
-          cart_of(cp.ld, id, dx, dy, dz);
-          kx[c] = (cx * (cp.ld + 1) + dx) * cp.tkrow;
-          ky[c] = cp.tkaxis + (cy * (cp.ld + 1) + dy) * cp.tkrow;
-          kz[c] = 2 * cp.tkaxis + (cz * (cp.ld + 1) + dz) * cp.tkrow;
-        } else {
-          const int zr = (cp.lc + 1) * (cp.ld + 1) * cp.tkrow;
-          kx[c] = zr;
-          ky[c] = cp.tkaxis + zr;
-          kz[c] = 2 * cp.tkaxis + zr;
-        }
-      }
-      d4 acc2[RB][C2G];
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int c = 0; c < C2G; ++c) acc2[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
-      gemm2<RB, C2G>(nrv, min(C2G, ncbw - g0), acc2, X, cp.xs, kete, qtab, kx, ky, kz, cp.nq4, lane);
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int c = 0; c < C2G; ++c) {
-          if (!cv[c] || !rbv[r]) continue;
-          const int cd = (wave + 8 * (g0 + c)) * 16 + (lane & 15);
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            const int ab = row0 + r * 16 + 4 * jj + (lane >> 4);
-            if (ab < cp.nab && cd < cp.ncd) {
-              double* o = out + qoff + (int64_t)ab * cp.ncd + cd;
-              if (kl == 0)
-                __builtin_nontemporal_store(acc2[r][c][jj], o);
-              else
-                *o += acc2[r][c][jj];
-            }
-          }
-        }
+    // second transform, written to HBM (accumulated over kl)
+    for (int g0 = 0; g0 < ncbw; g0 += kGroup) {
+      const int ng = min(kGroup, ncbw - g0);
+      const int cb0 = wave + 8 * g0;
+      const bool first = kl == 0;
+      if (ng == 4)
+        gemm2_group<NR, 4>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, lane);
+      else if (ng == 3)
+        gemm2_group<NR, 3>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, lane);
+      else if (ng == 2)
+        gemm2_group<NR, 2>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, lane);
+      else
+        gemm2_group<NR, 1>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, lane);
     }
     __syncthreads();
   }
+}
+
+// One workgroup = one quartet x one tile of RB*16 bra rows; 8 waves.
+template <int RB>
+__global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
+    const ClassParams cp, const double* __restrict__ boys_tab, const uint32_t* __restrict__ rtab_L,
+    const double* __restrict__ centers, const double* __restrict__ exps,
+    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, double* __restrict__ out,
+    int64_t q0) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
+  const int64_t q = q0 + blockIdx.x / cp.nrt;
+  const int rt = blockIdx.x % cp.nrt;
+  const int kmax = cp.kmax;
+
+  Lds s;
+  s.sh = (double*)(lds + cp.o_shell);
+  s.baseM = (double*)(lds + cp.o_base);
+  s.kpair = s.baseM + 32;
+  s.bpair = s.kpair + 16;
+  s.pqv = s.bpair + 16;
+  s.ptab = (int2*)(lds + cp.o_ptab);
+  s.qtab = (int2*)(lds + cp.o_qtab);
+  s.box = (double*)(lds + cp.o_union);
+  s.brae = (double*)(lds + cp.o_brae);
+  s.X = (double*)(lds + cp.o_union);
+  s.kete = (double*)(lds + cp.o_kete);
+  int* shn = (int*)(s.sh + 12 + 8 * kmax);
+
+  // shell data of this quartet
+  if (tid < 12) {
+    s.sh[tid] = centers[q * 12 + tid];
+  } else if (tid < 12 + 8 * kmax) {
+    const int j = tid - 12;
+    s.sh[tid] = (j < 4 * kmax) ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)];
+  } else if (tid >= 256 && tid < 260) {
+    shn[tid - 256] = nprim[q * 4 + (tid - 256)];
+  }
+  build_htab(s.ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, tid);
+  build_htab(s.qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, tid);
+  uint32_t rent[kRPerThread];
+  load_rtab(rent, rtab_L, cp.L, tid);
+  __syncthreads();
+
+  const int Ka = shn[0], Kb = shn[1], Kc = shn[2], Kd = shn[3];
+  const int row0 = rt * RB * 16;
+  if (Ka < 1 || Ka > kmax || Kb < 1 || Kb > kmax || Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax) {
+    const int nrows = min(RB * 16, cp.nab - row0);
+    double* o = out + q * (int64_t)cp.nab * cp.ncd + (int64_t)row0 * cp.ncd;
+    for (int i = tid; i < nrows * cp.ncd; i += kThreads) o[i] = __builtin_nan("");
+    return;
+  }
+  const int nc1 = (wave < cp.nqb) ? min(4, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
+  const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                       // valid row blocks of this tile
+#define BODY(NR, NC1) \
+  fused_body<NR, NC1>(cp, s, boys_tab, rent, out, q, rt, row0, Ka, Kb, Kc, Kd, tid, wave, lane)
+  constexpr int NR2 = RB >= 2 ? 2 : 1;
+  if (nrv == NR2 && NR2 == 2) {
+    switch (nc1) {
+      case 0: BODY(NR2, 0); break;
+      case 1: BODY(NR2, 1); break;
+      case 2: BODY(NR2, 2); break;
+      case 3: BODY(NR2, 3); break;
+      default: BODY(NR2, 4); break;
+    }
+  } else {
+    switch (nc1) {
+      case 0: BODY(1, 0); break;
+      case 1: BODY(1, 1); break;
+      case 2: BODY(1, 2); break;
+      case 3: BODY(1, 3); break;
+      default: BODY(1, 4); break;
+    }
+  }
+#undef BODY
 }
 
 // ---------------------------------------------------------------------------
@@ -557,7 +572,9 @@ __global__ __launch_bounds__(kThreads, 1) void hermite_r_kernel(
     baseM[tid] = pw * (2.0 * pow(M_PI, 2.5) / (a * b * sqrt(a + b))) * boys_fm(tid, T, boys_tab);
   }
   __syncthreads();
-  hermite_r_box(box, baseM, L, S1, S2, pq, rtab_L, tid);
+  uint32_t rent[kRPerThread];
+  load_rtab(rent, rtab_L, L, tid);
+  hermite_r_box(box, baseM, L, S1, S2, pq, rent, tid);
   double* o = R + it * (int64_t)n1 * n1 * n1;
   for (int e = tid; e < n1 * n1 * n1; e += kThreads) {
     const int t = e / S2, u = (e / S1) % n1, v = e % n1;
@@ -630,18 +647,17 @@ std::vector<DeviceState> g_dev;
     if (e_ != hipSuccess) return fail(ERI4_ERROR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-template <int RB, int C1>
+template <int RB>
 eri4_status set_attr_one() {
-  HIP_TRY(hipFuncSetAttribute((const void*)eri4_fused_kernel<RB, C1, 4>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes));
+  HIP_TRY(hipFuncSetAttribute((const void*)eri4_fused_kernel<RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxLdsBytes));
   return ERI4_SUCCESS;
 }
 
 eri4_status set_attrs() {
   eri4_status s;
-#define ONE(RB, C1) if ((s = set_attr_one<RB, C1>()) != ERI4_SUCCESS) return s;
-  ONE(1, 1) ONE(1, 2) ONE(1, 3) ONE(1, 4) ONE(2, 1) ONE(2, 2) ONE(2, 3) ONE(2, 4)
-#undef ONE
+  if ((s = set_attr_one<1>()) != ERI4_SUCCESS) return s;
+  if ((s = set_attr_one<2>()) != ERI4_SUCCESS) return s;
   HIP_TRY(hipFuncSetAttribute((const void*)hermite_r_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLdsBytes));
   return ERI4_SUCCESS;
@@ -714,11 +730,11 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb) {
   return p;
 }
 
-template <int RB, int C1>
+template <int RB>
 hipError_t launch_fused(const ClassParams& p, dim3 grid, hipStream_t s, const DeviceState* d,
                         const double* c, const double* e, const double* co, const int32_t* np, double* out,
                         int64_t q0) {
-  hipLaunchKernelGGL((eri4_fused_kernel<RB, C1, 4>), grid, dim3(kThreads), p.lds_bytes, s, p, d->boys,
+  hipLaunchKernelGGL((eri4_fused_kernel<RB>), grid, dim3(kThreads), p.lds_bytes, s, p, d->boys,
                      d->rtab + d->rstart[p.L], c, e, co, np, out, q0);
   return hipGetLastError();
 }
@@ -773,25 +789,14 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets, const 
   }
   if (p.lds_bytes > kMaxLdsBytes)
     return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) needs %d bytes of LDS", la, lb, lc, ld, p.lds_bytes);
-  const int c1 = (p.nqb + 7) / 8;
-  if (c1 > 4) return fail(ERI4_ERROR_INTERNAL, "no kernel variant for %d column blocks", p.nqb);
+  if (p.nqb > 32) return fail(ERI4_ERROR_INTERNAL, "no kernel variant for %d column blocks", p.nqb);
   const int64_t max_blocks = (int64_t)1 << 30;
   const int64_t qchunk = max_blocks / p.nrt;
   for (int64_t q0 = 0; q0 < nquartets; q0 += qchunk) {
     const int64_t nq = (nquartets - q0 < qchunk) ? nquartets - q0 : qchunk;
     const dim3 grid((unsigned)(nq * p.nrt));
-    hipError_t e = hipSuccess;
-    switch (rb * 10 + c1) {
-      case 11: e = launch_fused<1, 1>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
-      case 12: e = launch_fused<1, 2>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
-      case 13: e = launch_fused<1, 3>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
-      case 14: e = launch_fused<1, 4>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
-      case 21: e = launch_fused<2, 1>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
-      case 22: e = launch_fused<2, 2>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
-      case 23: e = launch_fused<2, 3>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
-      case 24: e = launch_fused<2, 4>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0); break;
-      default: return fail(ERI4_ERROR_INTERNAL, "no kernel variant");
-    }
+    const hipError_t e = (rb == 2) ? launch_fused<2>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0)
+                                   : launch_fused<1>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0);
     if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
   }
   return ERI4_SUCCESS;
