@@ -105,6 +105,7 @@ __device__ void build_etab(double* E, int la, int lb, int trow, int taxis, doubl
 #pragma unroll
       for (int t = 0; t < 16; ++t)
         if (t < trow) row[t] = (alt_sign && (t & 1)) ? -e[t] : e[t];
+      for (int t = 16; t < trow; ++t) row[t] = 0.0;  // beyond a+b <= 14
       if (b < lb) etab_step(e, h, pb);
     }
   }
@@ -156,34 +157,35 @@ __device__ void hermite_r_box(double* box, const double* baseM, int L, int S1, i
   const double px = PQ[0], py = PQ[1], pz = PQ[2];
   for (int m = L - 1; m >= 0; --m) {
     const int nact = nherm(L - m);
-    double nv[kRPerThread];
+    const int kact = (nact + kThreads - 1) / kThreads;  // entry slots in use at this level (uniform)
+    double v1[kRPerThread], v2[kRPerThread], c1[kRPerThread], c2[kRPerThread];
+    // all reads of the level first (inactive slots read box[0], which is in bounds)
 #pragma unroll
     for (int k = 0; k < kRPerThread; ++k) {
-      asm volatile("" : "+v"(ent[k]));
-      const int e = tid + k * kThreads;
-      nv[k] = 0.0;
-      if (e < nact) {
-        if (e == 0) {
-          nv[k] = baseM[m];
-        } else {
-          const uint32_t w = ent[k];
-          const int tgt = (int)(w & 0xffffu);
-          const int dir = (int)((w >> 16) & 3u);
-          const int ri = (int)((w >> 18) & 63u);
-          const int stride = dir == 0 ? S2 : (dir == 1 ? S1 : 1);
-          const double pq = dir == 0 ? px : (dir == 1 ? py : pz);
-          const int o1 = tgt - stride;
-          const int o2 = ri >= 2 ? o1 - stride : o1;
-          nv[k] = pq * box[o1] + (double)(ri - 1) * box[o2];
-        }
+      if (k < kact) {
+        asm volatile("" : "+v"(ent[k]));
+        const uint32_t w = ent[k];
+        const int tgt = (int)(w & 0xffffu);
+        const int dir = (int)((w >> 16) & 3u);
+        const int ri = (int)((w >> 18) & 63u);
+        const int stride = dir == 0 ? S2 : (dir == 1 ? S1 : 1);
+        const int o1 = max(tgt - stride, 0);
+        const int o2 = ri >= 2 ? tgt - 2 * stride : o1;
+        c1[k] = dir == 0 ? px : (dir == 1 ? py : pz);
+        c2[k] = (double)max(ri - 1, 0);
+        v1[k] = box[o1];
+        v2[k] = box[o2];
       }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kRPerThread; ++k) {
-      const int e = tid + k * kThreads;
-      if (e < nact) box[ent[k] & 0xffffu] = nv[k];
+      if (k < kact) {
+        const int e = tid + k * kThreads;
+        if (e < nact && e > 0) box[ent[k] & 0xffffu] = c1[k] * v1[k] + c2[k] * v2[k];
+      }
     }
+    if (tid == 0) box[0] = baseM[m];
     __syncthreads();
   }
 }
@@ -558,11 +560,11 @@ __global__ __launch_bounds__(kThreads, 1) void hermite_r_kernel(
   double* box = baseM + 32;
   const int tid = threadIdx.x;
   const int64_t it = blockIdx.x;
-  const int n1 = L + 1, S1 = n1, S2 = n1 * n1;
+  const int n1 = L + 1, S1 = box_s1(L), S2 = box_s2(L);
   const double a = zp[it], b = zq[it];
   double PQ[3];
   for (int x = 0; x < 3; ++x) PQ[x] = P[it * 3 + x] - Q[it * 3 + x];
-  double* pq = baseM + 32 + (L + 1) * (L + 1) * (L + 1);
+  double* pq = baseM + 32 + (L + 1) * S2;
   if (tid < 3) pq[tid] = PQ[tid];
   if (tid <= L) {
     const double rho = a * b / (a + b);
@@ -577,8 +579,8 @@ __global__ __launch_bounds__(kThreads, 1) void hermite_r_kernel(
   hermite_r_box(box, baseM, L, S1, S2, pq, rent, tid);
   double* o = R + it * (int64_t)n1 * n1 * n1;
   for (int e = tid; e < n1 * n1 * n1; e += kThreads) {
-    const int t = e / S2, u = (e / S1) % n1, v = e % n1;
-    o[e] = (t + u + v <= L) ? box[e] : 0.0;
+    const int t = e / (n1 * n1), u = (e / n1) % n1, v = e % n1;
+    o[e] = (t + u + v <= L) ? box[t * S2 + u * S1 + v] : 0.0;
   }
 }
 
@@ -589,7 +591,7 @@ __global__ void hermite_e_kernel(int la, int lb, const double* __restrict__ za, 
   double* tabs = (double*)lds;
   const int lane = threadIdx.x;
   const int64_t it = blockIdx.x;
-  const int trow = la + lb + 2;
+  const int trow = odd_row(la + lb + 2);
   const int taxis = ((la + 1) * (lb + 1) + 1) * trow;
   double* pair = tabs + 3 * taxis;
   if (lane == 0) {
@@ -707,8 +709,8 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb) {
   p.nqb = (p.nq + 15) / 16;
   p.ncdb = (p.ncd + 15) / 16;
   p.nrt = (p.nab + 16 * rb - 1) / (16 * rb);
-  p.S1 = p.L + 1; p.S2 = (p.L + 1) * (p.L + 1);
-  p.tbrow = p.Lb + 2; p.tkrow = p.Lk + 2;
+  p.S1 = box_s1(p.L); p.S2 = box_s2(p.L);
+  p.tbrow = odd_row(p.Lb + 2); p.tkrow = odd_row(p.Lk + 2);
   p.tbaxis = ((la + 1) * (lb + 1) + 1) * p.tbrow;
   p.tkaxis = ((lc + 1) * (ld + 1) + 1) * p.tkrow;
   p.xs = 16 * p.nqb + 2;
@@ -719,7 +721,7 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb) {
   p.o_ptab = off;  off = align16(off + p.np4 * 8);
   p.o_qtab = off;  off = align16(off + 16 * p.nqb * 8);
   p.o_union = off;
-  const int box_b = (p.L + 1) * (p.L + 1) * (p.L + 1) * 8;
+  const int box_b = (p.L + 1) * p.S2 * 8;
   const int ph1 = align16(box_b) + 3 * p.tbaxis * 8;
   const int xb = align16(rb * 16 * p.xs * 8);
   const int ph2 = xb + 3 * p.tkaxis * 8;
@@ -832,7 +834,7 @@ eri4_status eri4_hermite_r(int L, int64_t n, const double* zp, const double* zq,
   DeviceState* d;
   eri4_status s = ensure_device(&d);
   if (s != ERI4_SUCCESS) return s;
-  const int lds = (32 + (L + 1) * (L + 1) * (L + 1) + 4) * 8;
+  const int lds = (32 + (L + 1) * box_s2(L) + 4) * 8;
   hipLaunchKernelGGL(hermite_r_kernel, dim3((unsigned)n), dim3(kThreads), lds, stream, L, zp, zq, P, Q, R,
                      d->boys, d->rtab + d->rstart[L]);
   HIP_TRY(hipGetLastError());
@@ -851,7 +853,7 @@ eri4_status eri4_hermite_e(int la, int lb, int64_t n, const double* za, const do
   DeviceState* d;
   eri4_status s = ensure_device(&d);
   if (s != ERI4_SUCCESS) return s;
-  const int trow = la + lb + 2;
+  const int trow = odd_row(la + lb + 2);
   const int lds = (3 * ((la + 1) * (lb + 1) + 1) * trow + 16) * 8;
   hipLaunchKernelGGL(hermite_e_kernel, dim3((unsigned)n), dim3(64), lds, stream, la, lb, za, zb, A, B, E);
   HIP_TRY(hipGetLastError());

@@ -26,13 +26,22 @@ constexpr int kBoysCols = kMaxL + kBoysJ + 2;  // 37
 // (2m-1)!! sqrt(pi) / 2^(m+1) = Gamma(m+1/2)/2, so F_m(T) = c_m / (T^m sqrt(T)).
 constexpr int kBoysAsymRow = kBoysRows;
 
+// Strides of the R box used for total order L: offset(t,u,v) = t*S2 + u*S1 + v.
+// S1 is the even number >= L+1 so that entries of one total order, which sit
+// S1-1 doubles apart, spread over the LDS banks; S2 = S1*(L+1).
+__host__ __device__ constexpr int box_s1(int L) { return ((L + 1) & 1) ? L + 2 : L + 1; }
+__host__ __device__ constexpr int box_s2(int L) { return box_s1(L) * (L + 1); }
+// Odd row length >= n for the 1-d E tables (rows of one table read by the
+// lanes of a wave then fall in different LDS banks).
+__host__ __device__ constexpr int odd_row(int n) { return n | 1; }
+
 // Pyramidal number: Hermite functions with total order <= n.
 __host__ __device__ constexpr int nherm(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
 // Hermite recursion tables: for each L in 0..kMaxL, the nherm(L) triples
 // (t,u,v) with t+u+v <= L ordered by total order, each packed as
-//   bits 0..15  offset t*(L+1)^2 + u*(L+1) + v in the (L+1)^3 box,
+//   bits 0..15  offset t*box_s2(L) + u*box_s1(L) + v in the R box,
 //   bits 16..17 the axis raised by eq. (md1) to reach it (0 x, 1 y, 2 z;
 //               the last non-zero of t, u, v),
 //   bits 18..23 the index along that axis.
@@ -56,7 +65,7 @@ struct ClassParams {
   int nqb;         // 16-wide column blocks of [ab|q]
   int ncdb;        // 16-wide column blocks of (ab|cd)
   int nrt;         // row tiles per quartet
-  int S1, S2;      // strides of the (L+1)^3 box: u -> S1, t -> S2
+  int S1, S2;      // strides of the R box: u -> S1, t -> S2 (box_s1, box_s2)
   int tbrow, tkrow;    // 1-d E table row lengths (Lb+2, Lk+2); last entry is 0
   int tbaxis, tkaxis;  // doubles per axis of the bra / ket tables (incl. zero row)
   int xs;              // row stride (doubles) of the [ab|q] tile in LDS

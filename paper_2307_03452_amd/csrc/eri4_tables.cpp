@@ -51,12 +51,12 @@ void make_rtabs(std::vector<uint32_t>& tab, std::vector<int>& start) {
   start.assign(kMaxL + 2, 0);
   for (int L = 0; L <= kMaxL; ++L) {
     start[L] = (int)tab.size();
-    const int n1 = L + 1;
+    const int S1 = box_s1(L), S2 = box_s2(L);
     for (int n = 0; n <= L; ++n)
       for (int t = n; t >= 0; --t)
         for (int u = n - t; u >= 0; --u) {
           const int v = n - t - u;
-          const uint32_t off = (uint32_t)((t * n1 + u) * n1 + v);
+          const uint32_t off = (uint32_t)(t * S2 + u * S1 + v);
           uint32_t dir, ri;
           if (v > 0) {
             dir = 2;
