@@ -87,6 +87,55 @@ def time_gpu(wl, b, steps, warmup):
     return out, wall, launch_ms
 
 
+def md4_flops_batch(lq, nprim):
+    from paper_2307_03452_amd import metrics
+    tot = 0
+    for (la, lb, lc, ld), k in zip(lq.tolist(), nprim.tolist()):
+        tot += metrics.md4_flops(la, lb, lc, ld, k[0] * k[1], k[2] * k[3])
+    return tot
+
+
+def time_uneven(steps, warmup, nq=20000, seed=1004):
+    """Uneven batch in one persistent launch: all ordered classes in {4,5,6}^4,
+    Zipf(1.2) class counts, contraction length 1..8 per shell."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs
+    b = inputs.uneven_batch(nq=nq, seed=seed)
+    plan = eri4.Plan(b.lq, b.nprim, b.kmax)
+    d = lambda a: torch.from_numpy(a).cuda()
+    C, E, Co = d(b.centers), d(b.exps), d(b.coefs)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        plan.execute(C, E, Co, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(C, E, Co, out=out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    flops = md4_flops_batch(b.lq, b.nprim)
+    # parity on a few sampled quartets (largest and random)
+    import numpy as np
+    import oracle
+    off = plan.offsets()
+    # the oracle's cost grows with the product of the four contraction lengths:
+    # sample among quartets whose product is at most 16
+    cheap = np.flatnonzero(np.prod(b.nprim, axis=1) <= 16)
+    big = cheap[np.argmax(b.lq[cheap].sum(axis=1))]
+    idx = sorted({int(big), *np.random.default_rng(7).choice(cheap, 3, replace=False).tolist()})
+    err = 0.0
+    for q in idx:
+        s_ = inputs.subset(b, [q])
+        o = oracle.eri_md4(tuple(int(x) for x in b.lq[q]), s_.centers, s_.exps, s_.coefs, s_.nprim)[0]
+        g = out[off[q]:off[q] + o.size].cpu().numpy().reshape(o.shape)
+        err = max(err, float(np.abs(g - o).max() / max(np.abs(o).max(), 1e-250)))
+    return {"workload": f"uneven batch: {nq} quartets, 81 classes (la lb|lc ld) in {{4,5,6}}^4 with Zipf(1.2) "
+                        "counts, K per shell uniform in 1..8, exponents [0.05,200], one persistent launch",
+            "value": plan.output_size / wall, "unit": "integrals/s", "ms_per_step": wall * 1e3,
+            "md4_tflops": flops / wall / 1e12, "pct_fp64_peak": 100 * flops / wall / 1e12 / FP64_PEAK_TFLOPS,
+            "parity_max_rel_err_sampled": err, "quartets": nq}
+
+
 def parity_sample(wl, b, out, n=2):
     import numpy as np
     import oracle
@@ -129,6 +178,8 @@ def main():
     ap.add_argument("--workload", default="iiii_k1", choices=sorted(WORKLOADS))
     ap.add_argument("--secondary-steps", type=int, default=1,
                     help="timed steps of the contracted (ii|ii) K=5 batch reported beside the headline (0: skip)")
+    ap.add_argument("--uneven-steps", type=int, default=1,
+                    help="timed steps of the 20k-quartet mixed-class batch reported beside the headline (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -179,6 +230,8 @@ def main():
         rec["secondary"] = {"workload": wl5["desc"], "value": ints / (wall5 / args.secondary_steps),
                             "unit": "integrals/s", "ms_per_step": wall5 * 1e3 / args.secondary_steps,
                             "md4_tflops": f5 / s5 / 1e12, "pct_fp64_peak": 100 * f5 / s5 / 1e12 / FP64_PEAK_TFLOPS}
+    if args.uneven_steps > 0 and args.workload == "iiii_k1":
+        rec["uneven"] = time_uneven(args.uneven_steps, 1)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

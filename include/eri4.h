@@ -51,7 +51,7 @@ typedef enum {
 } eri4_status;
 
 /* Largest angular momentum per shell accepted by eri4_batch. */
-#define ERI4_MAX_L 6
+#define ERI4_MAX_L 7
 /* Largest contraction length per shell (kmax) accepted by eri4_batch. */
 #define ERI4_MAX_K 16
 /* Largest Boys order m accepted by eri4_boys (covers L = 4 * 7). */
@@ -105,6 +105,47 @@ eri4_status eri4_init(void);
 eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets,
                        const double* centers, const double* exponents, const double* coeffs,
                        const int32_t* nprim, int kmax, double* out, hipStream_t stream);
+
+/*
+ * Plans -- one batch mixing classes and contraction lengths, computed by a single
+ * persistent launch (Sec. 3, batched evaluation; the paper groups shell pairs of
+ * equal total angular momentum and contraction order into lists, here the
+ * grouping is per work item inside one launch).
+ *
+ * eri4_plan_create reads the HOST arrays
+ *   l      int32 [nquartets][4]   angular momenta of shells a, b, c, d, 0..ERI4_MAX_L
+ *   nprim  int32 [nquartets][4]   contraction lengths, 1..kmax
+ * splits every quartet into tiles of bra rows, orders the tiles by an estimate
+ * of their cost (largest first) and uploads the schedule, the per-class
+ * parameters, the output offsets and a copy of nprim to device memory that the
+ * plan owns.  It allocates and synchronises; everything else about a plan does
+ * neither.  Errors: INVALID_ARGUMENT (sizes, NULL, a length outside 1..kmax),
+ * UNSUPPORTED (l > ERI4_MAX_L), OUT_OF_MEMORY, HIP.  On error *plan is NULL.
+ *
+ * Output layout: quartet q's (ab|cd) block, [Na][Nb][Nc][Nd] row-major for its
+ * own class, starts at offsets[q] doubles into out, quartets in input order
+ * with no gaps; eri4_plan_output_size gives the total number of doubles.
+ *
+ * eri4_plan_execute enqueues on `stream` a one-thread counter reset and the
+ * persistent kernel; it neither allocates nor synchronises, so it can be
+ * captured into a HIP graph and replayed.  centers, exponents and coeffs are
+ * device arrays laid out as for eri4_batch ([nquartets][4][3], [nquartets][4][kmax]);
+ * the contraction lengths are the ones given at creation.  Executions of one
+ * plan must not overlap in time (they share the plan's work counter); run them
+ * on one stream or order them.  The plan must be executed on the device that
+ * was current at creation.
+ *
+ * eri4_plan_destroy frees the plan's device memory (hipFree synchronises).
+ */
+typedef struct eri4_plan_s* eri4_plan;
+
+eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
+                             int kmax);
+int64_t eri4_plan_output_size(eri4_plan plan);                         /* doubles; -1 if plan is NULL */
+eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets); /* HOST int64 [nquartets] */
+eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents,
+                              const double* coeffs, double* out, hipStream_t stream);
+eri4_status eri4_plan_destroy(eri4_plan plan);
 
 /*
  * Stage entry points.  They run the same device code the fused eri4_batch

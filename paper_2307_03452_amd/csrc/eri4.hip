@@ -20,10 +20,14 @@
 // Gaussian-product prefactors and contraction coefficients into [0]^(m).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <mutex>
+#include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -112,10 +116,11 @@ __device__ void build_etab(double* E, int la, int lb, int trow, int taxis, doubl
 }
 
 // Hermite index table: ordinal -> (t,u,v) in lexicographic order over
-// t+u+v <= Lh, packed t | u<<8 | v<<16 together with the offset in the R box.
-// Entries n..n_alloc-1 are padding: (Lh+1, 0, 0) (an E index whose value is 0)
-// and box offset 0.
-__device__ void build_htab(int2* tab, int Lh, int n, int n_alloc, int S1, int S2, int tid) {
+// t+u+v <= Lh, packed t | u<<8 | v<<16 | t<<24 together with its part of the R
+// offset (box: t*S2 + u*S1 + v; slab: u*S1 + v, the slab of the summed t,
+// taken from bits 24.., is added per gather).  Entries n..n_alloc-1 are
+// padding: E index (Lh+1, 0, 0), whose value is 0, and R index (0,0,0).
+__device__ void build_htab(int2* tab, int Lh, int n, int n_alloc, int S1, int S2, bool slab, int tid) {
   const int ncol = (Lh + 1) * (Lh + 2) / 2;
   for (int c = tid; c < ncol; c += kThreads) {
     int t = 0, rem = c;
@@ -127,7 +132,7 @@ __device__ void build_htab(int2* tab, int Lh, int n, int n_alloc, int S1, int S2
     // triples before column (t,u): all with a smaller t, then columns u' < u of this t
     const int first = (nherm(Lh) - nherm(Lh - t)) + u * (2 * (Lh - t) + 3 - u) / 2;
     for (int v = 0; v <= Lh - t - u; ++v)
-      tab[first + v] = make_int2(t | (u << 8) | (v << 16), t * S2 + u * S1 + v);
+      tab[first + v] = make_int2(t | (u << 8) | (v << 16) | (t << 24), (slab ? 0 : t * S2) + u * S1 + v);
   }
   for (int i = n + tid; i < n_alloc; i += kThreads) tab[i] = make_int2(Lh + 1, 0);
 }
@@ -141,62 +146,57 @@ __device__ __forceinline__ void cart_of(int l, int i, int& x, int& y, int& z) {
   x = l - n;
 }
 
-// [r]^(0) for |r| <= L in the (L+1)^3 LDS box, by eq. (md1) for decreasing m,
-// overwriting [r]^(m+1) with [r]^(m).  Each level is computed into registers
-// (up to kRPerThread entries per thread), then written after a barrier.
+// [r]^(0) for |r| <= L in LDS (box or slab layout, encoded in the table), by
+// eq. (md1) for decreasing m, overwriting [r]^(m+1) with [r]^(m).  Each level
+// reads all its operands into registers, then writes after a barrier.
 // baseM[m] holds [0]^(m); PQ (3 doubles, LDS) is P - Q.  ent[] holds this
-// thread's packed recursion-table entries; they are made opaque every level so
-// that only the 32-bit entries stay live, not their decoded form.
-__device__ void hermite_r_box(double* box, const double* baseM, int L, int S1, int S2,
-                              const double* PQ, const uint32_t (&ent_in)[kRPerThread], int tid) {
-  uint32_t ent[kRPerThread];
+// thread's recursion-table entries; they are made opaque every level so that
+// only the packed words stay live, not their decoded form.
+template <int NE>
+__device__ void hermite_r_lds(double* R, const double* baseM, int L, const double* PQ, const uint2 (&ent_in)[NE],
+                              int tid) {
+  uint2 ent[NE];
 #pragma unroll
-  for (int k = 0; k < kRPerThread; ++k) ent[k] = ent_in[k];
-  if (tid == 0) box[0] = baseM[L];
+  for (int k = 0; k < NE; ++k) ent[k] = ent_in[k];
+  if (tid == 0) R[0] = baseM[L];
   __syncthreads();
   const double px = PQ[0], py = PQ[1], pz = PQ[2];
   for (int m = L - 1; m >= 0; --m) {
     const int nact = nherm(L - m);
     const int kact = (nact + kThreads - 1) / kThreads;  // entry slots in use at this level (uniform)
-    double v1[kRPerThread], v2[kRPerThread], c1[kRPerThread], c2[kRPerThread];
-    // all reads of the level first (inactive slots read box[0], which is in bounds)
+    double nv[NE];
 #pragma unroll
-    for (int k = 0; k < kRPerThread; ++k) {
+    for (int k = 0; k < NE; ++k) {
       if (k < kact) {
-        asm volatile("" : "+v"(ent[k]));
-        const uint32_t w = ent[k];
-        const int tgt = (int)(w & 0xffffu);
-        const int dir = (int)((w >> 16) & 3u);
-        const int ri = (int)((w >> 18) & 63u);
-        const int stride = dir == 0 ? S2 : (dir == 1 ? S1 : 1);
-        const int o1 = max(tgt - stride, 0);
-        const int o2 = ri >= 2 ? tgt - 2 * stride : o1;
-        c1[k] = dir == 0 ? px : (dir == 1 ? py : pz);
-        c2[k] = (double)max(ri - 1, 0);
-        v1[k] = box[o1];
-        v2[k] = box[o2];
+        asm volatile("" : "+v"(ent[k].x), "+v"(ent[k].y));
+        const int o1 = (int)(ent[k].x >> 16);
+        const int o2 = (int)(ent[k].y & 0xffffu);
+        const int dir = (int)((ent[k].y >> 16) & 3u);
+        const int ri = (int)(ent[k].y >> 18);
+        const double c1 = dir == 0 ? px : (dir == 1 ? py : pz);
+        nv[k] = c1 * R[o1] + (double)max(ri - 1, 0) * R[o2];
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kRPerThread; ++k) {
+    for (int k = 0; k < NE; ++k) {
       if (k < kact) {
         const int e = tid + k * kThreads;
-        if (e < nact && e > 0) box[ent[k] & 0xffffu] = c1[k] * v1[k] + c2[k] * v2[k];
+        if (e < nact && e > 0) R[ent[k].x & 0xffffu] = nv[k];
       }
     }
-    if (tid == 0) box[0] = baseM[m];
+    if (tid == 0) R[0] = baseM[m];
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ void load_rtab(uint32_t (&ent)[kRPerThread], const uint32_t* __restrict__ rt,
-                                          int L, int tid) {
+template <int NE>
+__device__ __forceinline__ void load_rtab(uint2 (&ent)[NE], const uint2* __restrict__ rt, int L, int tid) {
   const int n = nherm(L);
 #pragma unroll
-  for (int k = 0; k < kRPerThread; ++k) {
+  for (int k = 0; k < NE; ++k) {
     const int e = tid + k * kThreads;
-    ent[k] = (e < n) ? rt[e] : 0u;
+    ent[k] = (e < n) ? rt[e] : make_uint2(0u, 0u);
   }
 }
 
@@ -229,15 +229,16 @@ __device__ __forceinline__ void make_pair(double* out, double za, double zb, dou
 //   acc[r][c] += sum_p E_ab[row block r][p] * box[off(p) + off(q in block c)]
 // E_ab is the product of three bra-table entries.  All LDS reads of a k step
 // are issued before its MFMAs; the next p index is fetched one step ahead.
-template <int NR, int NC>
+template <int NR, int NC, bool SLAB>
 __device__ __forceinline__ void gemm1_pair(d4 (&acc)[NR][NC], const double* __restrict__ brae,
-                                           const double* __restrict__ box, const int2* __restrict__ ptab,
+                                           const double* __restrict__ R, const int2* __restrict__ ptab,
                                            const int (&rowx)[NR], const int (&rowy)[NR], const int (&rowz)[NR],
-                                           const int (&offq)[NC], int np4, int lane) {
+                                           const int (&offq)[NC], const int (&tq)[NC], int np4, int L, int S1,
+                                           int lane) {
   const int g = lane >> 4;
   int2 pt = ptab[g];
   for (int kk = 0; kk < np4; kk += 4) {
-    const int tp = pt.x & 0xff, up = (pt.x >> 8) & 0xff, vp = pt.x >> 16;
+    const int tp = pt.x & 0xff, up = (pt.x >> 8) & 0xff, vp = (pt.x >> 16) & 0xff;
     double ex[NR], ey[NR], ez[NR], b[NC];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -246,7 +247,14 @@ __device__ __forceinline__ void gemm1_pair(d4 (&acc)[NR][NC], const double* __re
       ez[r] = brae[rowz[r] + vp];
     }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) b[c] = box[pt.y + offq[c]];
+    for (int c = 0; c < NC; ++c) {
+      if constexpr (SLAB) {
+        const int t = (pt.x >> 24) + tq[c];  // t of p+q selects the slab
+        b[c] = R[slab_base(t, L, S1) + pt.y + offq[c]];
+      } else {
+        b[c] = R[pt.y + offq[c]];
+      }
+    }
     pt = ptab[min(kk + 4, np4 - 4) + g];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -293,7 +301,7 @@ __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double*
   const int xs = cp.xs, nq4 = cp.nq4;
   int pk = qtab[g].x;
   for (int kk = 0; kk < nq4; kk += 4) {
-    const int tq = pk & 0xff, uq = (pk >> 8) & 0xff, vq = pk >> 16;
+    const int tq = pk & 0xff, uq = (pk >> 8) & 0xff, vq = (pk >> 16) & 0xff;
     double a[NR], fx[NC], fy[NC], fz[NC];
 #pragma unroll
     for (int r = 0; r < NR; ++r) a[r] = X[(r * 16 + n) * xs + kk + g];
@@ -340,9 +348,9 @@ constexpr int kGroup = 4;  // output column blocks per second-transform pass
 
 // Everything a workgroup does after its prologue, for NR valid row blocks and
 // NC1 first-transform column blocks of this wave.
-template <int NR, int NC1>
+template <int NR, int NC1, bool SLAB>
 __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, const double* __restrict__ boys_tab,
-                           const uint32_t (&rent)[kRPerThread], double* __restrict__ out, int64_t q, int rt,
+                           const uint2 (&rent)[SLAB ? kRPerThread : kRPerBox], double* __restrict__ outq,
                            int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane) {
   const int kmax = cp.kmax;
   const double* A = s.sh;
@@ -374,13 +382,16 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
     }
   }
   // [ab|q] columns of this lane (B operand of the first transform)
-  int offq[NC1A];
+  int offq[NC1A], tq[NC1A];
 #pragma unroll
-  for (int c = 0; c < NC1A; ++c) offq[c] = (c < NC1) ? s.qtab[(wave + 8 * c) * 16 + (lane & 15)].y : 0;
+  for (int c = 0; c < NC1A; ++c) {
+    const int2 e = (c < NC1) ? s.qtab[(wave + 8 * c) * 16 + (lane & 15)] : make_int2(0, 0);
+    offq[c] = e.y;
+    tq[c] = (int)((unsigned)e.x >> 24);
+  }
   const int ncbw = (wave < cp.ncdb) ? (cp.ncdb - wave + 7) / 8 : 0;  // output column blocks of this wave
 
   const double pref = 2.0 * pow(M_PI, 2.5);
-  double* outq = out + q * (int64_t)cp.nab * cp.ncd;
 
   for (int kl = 0; kl < Kc * Kd; ++kl) {
     if (tid == 0) {
@@ -421,9 +432,10 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
                    lane);
       }
       __syncthreads();
-      hermite_r_box(s.box, s.baseM, cp.L, cp.S1, cp.S2, s.pqv, rent, tid);
+      hermite_r_lds(s.box, s.baseM, cp.L, s.pqv, rent, tid);
       // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
-      if constexpr (NC1 > 0) gemm1_pair<NR, NC1>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, cp.np4, lane);
+      if constexpr (NC1 > 0)
+        gemm1_pair<NR, NC1, SLAB>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, tq, cp.np4, cp.L, cp.S1, lane);
       __syncthreads();
     }
 
@@ -461,20 +473,17 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
   }
 }
 
-// One workgroup = one quartet x one tile of RB*16 bra rows; 8 waves.
-template <int RB>
-__global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
-    const ClassParams cp, const double* __restrict__ boys_tab, const uint32_t* __restrict__ rtab_L,
-    const double* __restrict__ centers, const double* __restrict__ exps,
-    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, double* __restrict__ out,
-    int64_t q0) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
-  const int64_t q = q0 + blockIdx.x / cp.nrt;
-  const int rt = blockIdx.x % cp.nrt;
+// All the work of one tile: quartet q, bra rows rt*RB*16.., whose integrals
+// start at outq.  Called by every thread of the workgroup; ends with a barrier.
+template <int RB, bool SLAB>
+__device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned char* lds,
+                                             const double* __restrict__ boys_tab,
+                                             const uint2* __restrict__ rtab_L,
+                                             const double* __restrict__ centers, const double* __restrict__ exps,
+                                             const double* __restrict__ coefs, const int32_t* __restrict__ nprim,
+                                             double* __restrict__ outq, int64_t q, int rt, int tid, int wave,
+                                             int lane) {
   const int kmax = cp.kmax;
-
   Lds s;
   s.sh = (double*)(lds + cp.o_shell);
   s.baseM = (double*)(lds + cp.o_base);
@@ -498,9 +507,9 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
   } else if (tid >= 256 && tid < 260) {
     shn[tid - 256] = nprim[q * 4 + (tid - 256)];
   }
-  build_htab(s.ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, tid);
-  build_htab(s.qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, tid);
-  uint32_t rent[kRPerThread];
+  build_htab(s.ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, SLAB, tid);
+  build_htab(s.qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, SLAB, tid);
+  uint2 rent[SLAB ? kRPerThread : kRPerBox];
   load_rtab(rent, rtab_L, cp.L, tid);
   __syncthreads();
 
@@ -508,14 +517,14 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
   const int row0 = rt * RB * 16;
   if (Ka < 1 || Ka > kmax || Kb < 1 || Kb > kmax || Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax) {
     const int nrows = min(RB * 16, cp.nab - row0);
-    double* o = out + q * (int64_t)cp.nab * cp.ncd + (int64_t)row0 * cp.ncd;
+    double* o = outq + (int64_t)row0 * cp.ncd;
     for (int i = tid; i < nrows * cp.ncd; i += kThreads) o[i] = __builtin_nan("");
+    __syncthreads();
     return;
   }
-  const int nc1 = (wave < cp.nqb) ? min(4, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
-  const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                       // valid row blocks of this tile
-#define BODY(NR, NC1) \
-  fused_body<NR, NC1>(cp, s, boys_tab, rent, out, q, rt, row0, Ka, Kb, Kc, Kd, tid, wave, lane)
+  const int nc1 = (wave < cp.nqb) ? min(kMaxC1, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
+  const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                             // valid row blocks of this tile
+#define BODY(NR, NC1) fused_body<NR, NC1, SLAB>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane)
   constexpr int NR2 = RB >= 2 ? 2 : 1;
   if (nrv == NR2 && NR2 == 2) {
     switch (nc1) {
@@ -524,6 +533,16 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
       case 2: BODY(NR2, 2); break;
       case 3: BODY(NR2, 3); break;
       default: BODY(NR2, 4); break;
+    }
+  } else if constexpr (SLAB) {
+    switch (nc1) {
+      case 0: BODY(1, 0); break;
+      case 1: BODY(1, 1); break;
+      case 2: BODY(1, 2); break;
+      case 3: BODY(1, 3); break;
+      case 4: BODY(1, 4); break;
+      case 5: BODY(1, 5); break;
+      default: BODY(1, 6); break;
     }
   } else {
     switch (nc1) {
@@ -535,6 +554,69 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
     }
   }
 #undef BODY
+}
+
+// One workgroup = one quartet x one tile of RB*16 bra rows; 8 waves.  Grid:
+// quartets q0.. in order, cp.nrt tiles each.
+template <int RB, bool SLAB>
+__global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
+    const ClassParams cp, const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
+    const double* __restrict__ centers, const double* __restrict__ exps,
+    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, double* __restrict__ out,
+    int64_t q0) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
+  const int64_t q = q0 + blockIdx.x / cp.nrt;
+  const int rt = blockIdx.x % cp.nrt;
+  process_tile<RB, SLAB>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
+                         out + q * (int64_t)cp.nab * cp.ncd, q, rt, tid, wave, lane);
+}
+
+// Persistent kernel for a plan: work items {quartet, row tile | class << 16},
+// largest first, taken from a device counter until none are left (every
+// workgroup exits once the counter passes nitems).  qoff[q] is where quartet
+// q's integrals start in out.  Each class brings its own tile height and R
+// layout.
+__global__ __launch_bounds__(kThreads, 1) void eri4_plan_kernel(
+    const ClassParams* __restrict__ classes, const int2* __restrict__ items, int nitems,
+    const int64_t* __restrict__ qoff, const int32_t* __restrict__ nprim, int* __restrict__ counter,
+    const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
+    const double* __restrict__ centers, const double* __restrict__ exps,
+    const double* __restrict__ coefs, double* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ int next_item;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (;;) {
+    if (tid == 0) next_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(next_item);
+    __syncthreads();
+    if (it >= nitems) break;
+    const int2 w = items[it];
+    const int q = __builtin_amdgcn_readfirstlane(w.x);
+    const int rc = __builtin_amdgcn_readfirstlane(w.y);
+    const ClassParams cp = classes[rc >> 16];
+    const int rt = rc & 0xffff;
+    const uint2* rt_L = rtab + cp.rtab_off;
+    double* oq = out + qoff[q];
+    if (cp.slab) {
+      if (cp.rb == 2)
+        process_tile<2, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+      else
+        process_tile<1, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+    } else {
+      if (cp.rb == 2)
+        process_tile<2, false>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+      else
+        process_tile<1, false>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+    }
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) {
+  if (threadIdx.x == 0) counter[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -552,19 +634,19 @@ __global__ void boys_kernel(int mmax, int64_t n, const double* __restrict__ T, d
 }
 
 __global__ __launch_bounds__(kThreads, 1) void hermite_r_kernel(
-    int L, const double* __restrict__ zp, const double* __restrict__ zq, const double* __restrict__ P,
+    int L, bool slab, const double* __restrict__ zp, const double* __restrict__ zq, const double* __restrict__ P,
     const double* __restrict__ Q, double* __restrict__ R, const double* __restrict__ boys_tab,
-    const uint32_t* __restrict__ rtab_L) {
+    const uint2* __restrict__ rtab_L) {
   extern __shared__ __align__(16) unsigned char lds[];
   double* baseM = (double*)lds;
-  double* box = baseM + 32;
+  double* pq = baseM + 32;
+  double* box = baseM + 36;
   const int tid = threadIdx.x;
   const int64_t it = blockIdx.x;
-  const int n1 = L + 1, S1 = box_s1(L), S2 = box_s2(L);
+  const int n1 = L + 1;
   const double a = zp[it], b = zq[it];
   double PQ[3];
   for (int x = 0; x < 3; ++x) PQ[x] = P[it * 3 + x] - Q[it * 3 + x];
-  double* pq = baseM + 32 + (L + 1) * S2;
   if (tid < 3) pq[tid] = PQ[tid];
   if (tid <= L) {
     const double rho = a * b / (a + b);
@@ -573,14 +655,14 @@ __global__ __launch_bounds__(kThreads, 1) void hermite_r_kernel(
     for (int mm = 0; mm < tid; ++mm) pw *= -2.0 * rho;
     baseM[tid] = pw * (2.0 * pow(M_PI, 2.5) / (a * b * sqrt(a + b))) * boys_fm(tid, T, boys_tab);
   }
-  __syncthreads();
-  uint32_t rent[kRPerThread];
+  uint2 rent[kRPerThread];
   load_rtab(rent, rtab_L, L, tid);
-  hermite_r_box(box, baseM, L, S1, S2, pq, rent, tid);
+  __syncthreads();
+  hermite_r_lds(box, baseM, L, pq, rent, tid);
   double* o = R + it * (int64_t)n1 * n1 * n1;
   for (int e = tid; e < n1 * n1 * n1; e += kThreads) {
     const int t = e / (n1 * n1), u = (e / n1) % n1, v = e % n1;
-    o[e] = (t + u + v <= L) ? box[t * S2 + u * S1 + v] : 0.0;
+    o[e] = (t + u + v <= L) ? box[r_offset(slab, L, t, u, v)] : 0.0;
   }
 }
 
@@ -636,8 +718,8 @@ eri4_status fail(eri4_status s, const char* fmt, ...) {
 struct DeviceState {
   bool ready = false;
   double* boys = nullptr;
-  uint32_t* rtab = nullptr;
-  int rstart[kMaxL + 2] = {0};
+  uint2* rtab = nullptr;
+  int rstart[2 * (kMaxL + 1)] = {0};  // [layout][L], in uint2 entries
 };
 
 std::mutex g_mu;
@@ -649,17 +731,21 @@ std::vector<DeviceState> g_dev;
     if (e_ != hipSuccess) return fail(ERI4_ERROR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-template <int RB>
+template <int RB, bool SLAB>
 eri4_status set_attr_one() {
-  HIP_TRY(hipFuncSetAttribute((const void*)eri4_fused_kernel<RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kMaxLdsBytes));
+  HIP_TRY(hipFuncSetAttribute((const void*)eri4_fused_kernel<RB, SLAB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes));
   return ERI4_SUCCESS;
 }
 
 eri4_status set_attrs() {
   eri4_status s;
-  if ((s = set_attr_one<1>()) != ERI4_SUCCESS) return s;
-  if ((s = set_attr_one<2>()) != ERI4_SUCCESS) return s;
+  if ((s = set_attr_one<1, false>()) != ERI4_SUCCESS) return s;
+  if ((s = set_attr_one<2, false>()) != ERI4_SUCCESS) return s;
+  if ((s = set_attr_one<1, true>()) != ERI4_SUCCESS) return s;
+  if ((s = set_attr_one<2, true>()) != ERI4_SUCCESS) return s;
+  HIP_TRY(hipFuncSetAttribute((const void*)eri4_plan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxLdsBytes - 64));
   HIP_TRY(hipFuncSetAttribute((const void*)hermite_r_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLdsBytes));
   return ERI4_SUCCESS;
@@ -679,14 +765,14 @@ eri4_status ensure_device(DeviceState** st) {
       make_boys_table(boys);
       make_rtabs(rt, rs);
     }
-    if ((int)rt.size() != kRtabTotal) return fail(ERI4_ERROR_INTERNAL, "recursion table size mismatch");
+    if ((int)rt.size() != 2 * 2 * kRtabEntries) return fail(ERI4_ERROR_INTERNAL, "recursion table size mismatch");
     if (hipMalloc(&d.boys, boys.size() * sizeof(double)) != hipSuccess)
       return fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation of the Boys table failed");
     if (hipMalloc(&d.rtab, rt.size() * sizeof(uint32_t)) != hipSuccess)
       return fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation of the recursion tables failed");
     HIP_TRY(hipMemcpy(d.boys, boys.data(), boys.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.rtab, rt.data(), rt.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    for (int L = 0; L <= kMaxL + 1; ++L) d.rstart[L] = rs[L];
+    for (int i = 0; i < 2 * (kMaxL + 1); ++i) d.rstart[i] = rs[i];
     eri4_status s = set_attrs();
     if (s != ERI4_SUCCESS) return s;
     d.ready = true;
@@ -698,8 +784,10 @@ eri4_status ensure_device(DeviceState** st) {
 int align16(int x) { return (x + 15) & ~15; }
 
 // Class parameters and LDS layout for a tile of rb*16 bra rows.
-ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb) {
+ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool slab) {
   ClassParams p{};
+  p.rb = rb;
+  p.slab = slab ? 1 : 0;
   p.la = la; p.lb = lb; p.lc = lc; p.ld = ld;
   p.na = ncart(la); p.nb = ncart(lb); p.nc = ncart(lc); p.nd = ncart(ld);
   p.nab = p.na * p.nb; p.ncd = p.nc * p.nd;
@@ -721,7 +809,7 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb) {
   p.o_ptab = off;  off = align16(off + p.np4 * 8);
   p.o_qtab = off;  off = align16(off + 16 * p.nqb * 8);
   p.o_union = off;
-  const int box_b = (p.L + 1) * p.S2 * 8;
+  const int box_b = r_cells(slab, p.L) * 8;
   const int ph1 = align16(box_b) + 3 * p.tbaxis * 8;
   const int xb = align16(rb * 16 * p.xs * 8);
   const int ph2 = xb + 3 * p.tkaxis * 8;
@@ -732,12 +820,28 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb) {
   return p;
 }
 
-template <int RB>
+// Class parameters: the first of (32-row tiles, box), (16, box), (32, slab),
+// (16, slab) that fits in LDS (limit: bytes available for the dynamic area).
+bool pick_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, int limit, ClassParams* out) {
+  const int rbs[4] = {2, 1, 2, 1};
+  const bool slabs[4] = {false, false, true, true};
+  for (int i = 0; i < 4; ++i) {
+    ClassParams p = make_params(la, lb, lc, ld, kmax, rbs[i], slabs[i]);
+    if (p.lds_bytes > limit || p.L > kMaxL || (p.nqb + 7) / 8 > (slabs[i] && rbs[i] == 1 ? kMaxC1 : 4)) continue;
+    if (!slabs[i] && p.L > kBoxLMax) continue;  // the box recursion holds kRPerBox entries per thread
+    p.rtab_off = d->rstart[(slabs[i] ? 1 : 0) * (kMaxL + 1) + p.L];
+    *out = p;
+    return true;
+  }
+  return false;
+}
+
+template <int RB, bool SLAB>
 hipError_t launch_fused(const ClassParams& p, dim3 grid, hipStream_t s, const DeviceState* d,
                         const double* c, const double* e, const double* co, const int32_t* np, double* out,
                         int64_t q0) {
-  hipLaunchKernelGGL((eri4_fused_kernel<RB>), grid, dim3(kThreads), p.lds_bytes, s, p, d->boys,
-                     d->rtab + d->rstart[p.L], c, e, co, np, out, q0);
+  hipLaunchKernelGGL((eri4_fused_kernel<RB, SLAB>), grid, dim3(kThreads), p.lds_bytes, s, p, d->boys, d->rtab, c,
+                     e, co, np, out, q0);
   return hipGetLastError();
 }
 
@@ -783,24 +887,208 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets, const 
   DeviceState* d;
   eri4_status s = ensure_device(&d);
   if (s != ERI4_SUCCESS) return s;
-  int rb = 2;
-  ClassParams p = make_params(la, lb, lc, ld, kmax, rb);
-  if (p.lds_bytes > kMaxLdsBytes) {
-    rb = 1;
-    p = make_params(la, lb, lc, ld, kmax, rb);
-  }
-  if (p.lds_bytes > kMaxLdsBytes)
-    return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) needs %d bytes of LDS", la, lb, lc, ld, p.lds_bytes);
-  if (p.nqb > 32) return fail(ERI4_ERROR_INTERNAL, "no kernel variant for %d column blocks", p.nqb);
+  ClassParams p;
+  if (!pick_params(la, lb, lc, ld, kmax, d, kMaxLdsBytes, &p))
+    return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
   const int64_t max_blocks = (int64_t)1 << 30;
   const int64_t qchunk = max_blocks / p.nrt;
   for (int64_t q0 = 0; q0 < nquartets; q0 += qchunk) {
     const int64_t nq = (nquartets - q0 < qchunk) ? nquartets - q0 : qchunk;
     const dim3 grid((unsigned)(nq * p.nrt));
-    const hipError_t e = (rb == 2) ? launch_fused<2>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0)
-                                   : launch_fused<1>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0);
+    hipError_t e;
+    if (p.slab)
+      e = (p.rb == 2) ? launch_fused<2, true>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0)
+                      : launch_fused<1, true>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0);
+    else
+      e = (p.rb == 2) ? launch_fused<2, false>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0)
+                      : launch_fused<1, false>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0);
     if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
   }
+  return ERI4_SUCCESS;
+}
+
+
+// ---------------------------------------------------------------------------
+// plans: many classes and contraction lengths in one persistent launch
+// ---------------------------------------------------------------------------
+
+struct eri4_plan_s {
+  int device = 0;
+  int64_t nq = 0;
+  int kmax = 1;
+  int nitems = 0;
+  int nclasses = 0;
+  int lds_bytes = 0;
+  int grid = 0;
+  int64_t out_size = 0;
+  std::vector<int64_t> qoff;
+  ClassParams* d_classes = nullptr;
+  int2* d_items = nullptr;
+  int64_t* d_qoff = nullptr;
+  int32_t* d_nprim = nullptr;
+  int* d_counter = nullptr;
+};
+
+static void plan_free(eri4_plan_s* p) {
+  if (!p) return;
+  if (p->d_classes) (void)hipFree(p->d_classes);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_qoff) (void)hipFree(p->d_qoff);
+  if (p->d_nprim) (void)hipFree(p->d_nprim);
+  if (p->d_counter) (void)hipFree(p->d_counter);
+  delete p;
+}
+
+eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim, int kmax) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
+  *plan = nullptr;
+  if (nquartets < 0 || nquartets > ((int64_t)1 << 31) - 1)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "nquartets must be in 0..2^31-1");
+  if (kmax < 1 || kmax > ERI4_MAX_K)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "kmax must be in 1..%d (got %d)", ERI4_MAX_K, kmax);
+  if (nquartets > 0 && (!l || !nprim)) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL host array");
+  for (int64_t i = 0; i < 4 * nquartets; ++i) {
+    if (l[i] < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "negative angular momentum at quartet %lld", (long long)(i / 4));
+    if (l[i] > ERI4_MAX_L)
+      return fail(ERI4_ERROR_UNSUPPORTED, "angular momentum %d above %d at quartet %lld", l[i], ERI4_MAX_L,
+                  (long long)(i / 4));
+    if (nprim[i] < 1 || nprim[i] > kmax)
+      return fail(ERI4_ERROR_INVALID_ARGUMENT, "contraction length %d outside 1..%d at quartet %lld", nprim[i], kmax,
+                  (long long)(i / 4));
+  }
+  DeviceState* d;
+  eri4_status st = ensure_device(&d);
+  if (st != ERI4_SUCCESS) return st;
+  eri4_plan_s* p = new (std::nothrow) eri4_plan_s();
+  if (!p) return fail(ERI4_ERROR_OUT_OF_MEMORY, "host allocation failed");
+  HIP_TRY(hipGetDevice(&p->device));
+  p->nq = nquartets;
+  p->kmax = kmax;
+
+  // classes present, keyed by (la,lb,lc,ld)
+  std::vector<int> cls_of_key(8 * 8 * 8 * 8, -1);
+  std::vector<int> qcls(nquartets);
+  std::vector<std::array<int, 4>> keys;
+  for (int64_t q = 0; q < nquartets; ++q) {
+    const int key = ((l[4 * q] * 8 + l[4 * q + 1]) * 8 + l[4 * q + 2]) * 8 + l[4 * q + 3];
+    if (cls_of_key[key] < 0) {
+      cls_of_key[key] = (int)keys.size();
+      keys.push_back({l[4 * q], l[4 * q + 1], l[4 * q + 2], l[4 * q + 3]});
+    }
+    qcls[q] = cls_of_key[key];
+  }
+  // per class: tile height and R layout (see pick_params)
+  std::vector<ClassParams> cps(keys.size());
+  for (size_t c = 0; c < keys.size(); ++c) {
+    if (!pick_params(keys[c][0], keys[c][1], keys[c][2], keys[c][3], kmax, d, kMaxLdsBytes - 64, &cps[c])) {
+      plan_free(p);
+      return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", keys[c][0], keys[c][1],
+                  keys[c][2], keys[c][3]);
+    }
+  }
+  p->nclasses = (int)keys.size();
+  for (const ClassParams& c : cps) p->lds_bytes = std::max(p->lds_bytes, c.lds_bytes);
+
+  // output offsets in input order, and work items with their cost
+  p->qoff.resize(nquartets);
+  int64_t off = 0;
+  std::vector<int2> items;
+  std::vector<double> cost;
+  for (int64_t q = 0; q < nquartets; ++q) {
+    const ClassParams& c = cps[qcls[q]];
+    p->qoff[q] = off;
+    off += (int64_t)c.nab * c.ncd;
+    const double kb = (double)nprim[4 * q] * nprim[4 * q + 1], kk = (double)nprim[4 * q + 2] * nprim[4 * q + 3];
+    for (int rt = 0; rt < c.nrt; ++rt) {
+      const int rows = 16 * std::min(c.rb, (c.nab - rt * c.rb * 16 + 15) / 16);
+      // MFMA cycles of the two transforms at 128 FLOP/clk per CU, plus a
+      // latency-bound estimate for Boys and the recursion per primitive quartet
+      const double g1 = 2.0 * rows * c.np4 * 16.0 * c.nqb * kb * kk;
+      const double g2 = 2.0 * rows * c.nq4 * 16.0 * c.ncdb * kk;
+      cost.push_back((g1 + g2) / 128.0 + kb * kk * (8000.0 + 4.0 * nherm(c.L)) + 4000.0);
+      items.push_back(make_int2((int)q, rt | (qcls[q] << 16)));
+    }
+  }
+  p->out_size = off;
+  std::vector<int> order(items.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<int2> sorted(items.size());
+  for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+  if (sorted.size() > (size_t)INT32_MAX) {
+    plan_free(p);
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "too many work items");
+  }
+  p->nitems = (int)sorted.size();
+
+  int ncu = 0, per_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
+  const hipError_t oe =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)eri4_plan_kernel, kThreads, p->lds_bytes);
+  if (oe != hipSuccess || per_cu < 1) per_cu = 1;
+  p->grid = (int)std::min<int64_t>(std::max(p->nitems, 1), (int64_t)ncu * per_cu);
+
+  const bool ok = hipMalloc(&p->d_classes, std::max<size_t>(1, cps.size()) * sizeof(ClassParams)) == hipSuccess &&
+                  hipMalloc(&p->d_items, std::max<size_t>(1, sorted.size()) * sizeof(int2)) == hipSuccess &&
+                  hipMalloc(&p->d_qoff, std::max<int64_t>(1, nquartets) * sizeof(int64_t)) == hipSuccess &&
+                  hipMalloc(&p->d_nprim, std::max<int64_t>(1, 4 * nquartets) * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(&p->d_counter, 64) == hipSuccess;
+  if (!ok) {
+    plan_free(p);
+    return fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation for the plan failed");
+  }
+  hipError_t e = hipSuccess;
+  if (!cps.empty()) e = hipMemcpy(p->d_classes, cps.data(), cps.size() * sizeof(ClassParams), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !sorted.empty())
+    e = hipMemcpy(p->d_items, sorted.data(), sorted.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess && nquartets > 0)
+    e = hipMemcpy(p->d_qoff, p->qoff.data(), nquartets * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && nquartets > 0)
+    e = hipMemcpy(p->d_nprim, nprim, 4 * nquartets * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return fail(ERI4_ERROR_HIP, "plan upload: %s", hipGetErrorString(e));
+  }
+  *plan = p;
+  return ERI4_SUCCESS;
+}
+
+int64_t eri4_plan_output_size(eri4_plan plan) { return plan ? plan->out_size : -1; }
+
+eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (plan->nq > 0 && !offsets) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL offsets array");
+  std::copy(plan->qoff.begin(), plan->qoff.end(), offsets);
+  return ERI4_SUCCESS;
+}
+
+eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents, const double* coeffs,
+                              double* out, hipStream_t stream) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (plan->nitems == 0) return ERI4_SUCCESS;
+  if (!centers || !exponents || !coeffs || !out) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != plan->device)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan was made for device %d, current device is %d", plan->device, dev);
+  DeviceState* d;
+  eri4_status st = ensure_device(&d);
+  if (st != ERI4_SUCCESS) return st;
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, plan->d_counter);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(eri4_plan_kernel, dim3(plan->grid), dim3(kThreads), plan->lds_bytes, stream, plan->d_classes,
+                     plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter, d->boys, d->rtab,
+                     centers, exponents, coeffs, out);
+  HIP_TRY(hipGetLastError());
+  return ERI4_SUCCESS;
+}
+
+eri4_status eri4_plan_destroy(eri4_plan plan) {
+  g_err.clear();
+  plan_free(plan);
   return ERI4_SUCCESS;
 }
 
@@ -834,9 +1122,10 @@ eri4_status eri4_hermite_r(int L, int64_t n, const double* zp, const double* zq,
   DeviceState* d;
   eri4_status s = ensure_device(&d);
   if (s != ERI4_SUCCESS) return s;
-  const int lds = (32 + (L + 1) * box_s2(L) + 4) * 8;
-  hipLaunchKernelGGL(hermite_r_kernel, dim3((unsigned)n), dim3(kThreads), lds, stream, L, zp, zq, P, Q, R,
-                     d->boys, d->rtab + d->rstart[L]);
+  const bool slab = (36 + r_cells(false, L)) * 8 > kMaxLdsBytes;
+  const int lds = (36 + r_cells(slab, L)) * 8;
+  hipLaunchKernelGGL(hermite_r_kernel, dim3((unsigned)n), dim3(kThreads), lds, stream, L, slab, zp, zq, P, Q, R,
+                     d->boys, d->rtab + d->rstart[(slab ? 1 : 0) * (kMaxL + 1) + L]);
   HIP_TRY(hipGetLastError());
   return ERI4_SUCCESS;
 }

@@ -39,20 +39,36 @@ __host__ __device__ constexpr int odd_row(int n) { return n | 1; }
 __host__ __device__ constexpr int nherm(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
-// Hermite recursion tables: for each L in 0..kMaxL, the nherm(L) triples
-// (t,u,v) with t+u+v <= L ordered by total order, each packed as
-//   bits 0..15  offset t*box_s2(L) + u*box_s1(L) + v in the R box,
-//   bits 16..17 the axis raised by eq. (md1) to reach it (0 x, 1 y, 2 z;
-//               the last non-zero of t, u, v),
-//   bits 18..23 the index along that axis.
-// rtab_start[L] is the first entry of table L.
-constexpr int kRtabTotal = 35960;  // sum_{L=0}^{28} nherm(L)
+// Two LDS layouts of the Hermite integrals [r] with t+u+v <= L:
+//   box  (L+1)^3 cells:   offset = t*S2 + u*S1 + v,        S2 = S1*(L+1)
+//   slab t-slabs of (L+1-t) rows: offset = slab_base(t) + u*S1 + v
+// The box makes the index p+q of eq. (pq) an address sum; the slab needs one
+// more term (slab_base of the summed t) but about half the space, which is
+// what lets L = 26, 28 fit in LDS.
+__host__ __device__ constexpr int slab_base(int t, int L, int S1) { return S1 * (t * (2 * L + 3 - t) / 2); }
+__host__ __device__ constexpr int r_cells(bool slab, int L) {
+  return slab ? box_s1(L) * (L + 1) * (L + 2) / 2 : (L + 1) * box_s2(L);
+}
+__host__ __device__ constexpr int r_offset(bool slab, int L, int t, int u, int v) {
+  return (slab ? slab_base(t, L, box_s1(L)) : t * box_s2(L)) + u * box_s1(L) + v;
+}
 
-// One workgroup computes a tile of kRowBlocks*16 bra rows (ab) of one quartet.
+// Hermite recursion tables: for each layout (0 box, 1 slab) and each L in
+// 0..kMaxL, the nherm(L) triples (t,u,v) with t+u+v <= L ordered by total
+// order, each as two 32-bit words
+//   x: offset of (t,u,v) | offset of (t,u,v) - 1_i << 16
+//   y: offset of (t,u,v) - 2*1_i (or of -1_i when r_i < 2) | i << 16 | r_i << 18
+// where i is the axis eq. (md1) raises to reach (t,u,v) (the last non-zero of
+// t, u, v).  The first entry of each table is (0,0,0) with all fields 0.
+constexpr int kRtabEntries = 35960;  // sum_{L=0}^{28} nherm(L), per layout
+
+// One workgroup computes a tile of 16 or 32 bra rows (ab) of one quartet.
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * 64;
-constexpr int kBoxLMax = 24;  // largest L whose (L+1)^3 box fits in LDS
-constexpr int kRPerThread = (nherm(kBoxLMax) + kThreads - 1) / kThreads;  // 6
+constexpr int kRPerThread = (nherm(kMaxL) + kThreads - 1) / kThreads;  // 9, slab layout (L <= 28)
+constexpr int kBoxLMax = 24;                                              // box layout only up to here
+constexpr int kRPerBox = (nherm(kBoxLMax) + kThreads - 1) / kThreads;     // 6
+constexpr int kMaxC1 = 6;  // first-transform column blocks per wave (L_ket <= 14)
 
 // Everything the fused kernel needs to know about one class (la lb|lc ld).
 struct ClassParams {
@@ -70,6 +86,9 @@ struct ClassParams {
   int tbaxis, tkaxis;  // doubles per axis of the bra / ket tables (incl. zero row)
   int xs;              // row stride (doubles) of the [ab|q] tile in LDS
   int kmax;
+  int rtab_off;        // first entry (uint2 units) of the recursion table for this layout and L
+  int slab;            // R layout: 0 box, 1 slab
+  int rb;              // 16-row blocks per tile (1 or 2)
   // LDS layout (byte offsets)
   int o_union;   // phase 1: R box then bra tables; phase 2: [ab|q] tile then ket tables
   int o_brae;    // bra tables (phase 1)

@@ -45,33 +45,39 @@ void make_boys_table(std::vector<double>& tab) {
 }
 
 // Triples (t,u,v), t+u+v <= L, by total order; within one total order any
-// order works because entries of one order only read lower orders.
+// order works because entries of one order only read lower orders.  Layout 0
+// (box) comes first, then layout 1 (slab); start[layout*(kMaxL+1) + L] is the
+// first entry (in uint32 pairs) of a table.
 void make_rtabs(std::vector<uint32_t>& tab, std::vector<int>& start) {
   tab.clear();
-  start.assign(kMaxL + 2, 0);
-  for (int L = 0; L <= kMaxL; ++L) {
-    start[L] = (int)tab.size();
-    const int S1 = box_s1(L), S2 = box_s2(L);
-    for (int n = 0; n <= L; ++n)
-      for (int t = n; t >= 0; --t)
-        for (int u = n - t; u >= 0; --u) {
-          const int v = n - t - u;
-          const uint32_t off = (uint32_t)(t * S2 + u * S1 + v);
-          uint32_t dir, ri;
-          if (v > 0) {
-            dir = 2;
-            ri = v;
-          } else if (u > 0) {
-            dir = 1;
-            ri = u;
-          } else {
-            dir = 0;
-            ri = t;
+  start.assign(2 * (kMaxL + 1), 0);
+  for (int layout = 0; layout < 2; ++layout)
+    for (int L = 0; L <= kMaxL; ++L) {
+      start[layout * (kMaxL + 1) + L] = (int)(tab.size() / 2);
+      const bool slab = layout == 1;
+      for (int n = 0; n <= L; ++n)
+        for (int t = n; t >= 0; --t)
+          for (int u = n - t; u >= 0; --u) {
+            const int v = n - t - u;
+            const uint32_t off = (uint32_t)r_offset(slab, L, t, u, v);
+            uint32_t dir = 0, ri = 0, o1 = 0, o2 = 0;
+            if (n > 0) {
+              int a[3] = {t, u, v};
+              dir = v > 0 ? 2 : (u > 0 ? 1 : 0);
+              ri = (uint32_t)a[dir];
+              a[dir] -= 1;
+              o1 = (uint32_t)r_offset(slab, L, a[0], a[1], a[2]);
+              if (ri >= 2) {
+                a[dir] -= 1;
+                o2 = (uint32_t)r_offset(slab, L, a[0], a[1], a[2]);
+              } else {
+                o2 = o1;
+              }
+            }
+            tab.push_back(off | (o1 << 16));
+            tab.push_back(o2 | (dir << 16) | (ri << 18));
           }
-          tab.push_back(off | (dir << 16) | (ri << 18));
-        }
-  }
-  start[kMaxL + 1] = (int)tab.size();
+    }
 }
 
 }  // namespace eri4

@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liberi4.so")
 
-ERI4_MAX_L = 6
+ERI4_MAX_L = 7
 ERI4_MAX_K = 16
 ERI4_MAX_BOYS_M = 28
 
@@ -22,7 +22,8 @@ STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UN
 
 # every symbol include/eri4.h declares
 EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version", "eri4_init",
-           "eri4_batch", "eri4_boys", "eri4_hermite_r", "eri4_hermite_e")
+           "eri4_batch", "eri4_plan_create", "eri4_plan_output_size", "eri4_plan_output_offsets",
+           "eri4_plan_execute", "eri4_plan_destroy", "eri4_boys", "eri4_hermite_r", "eri4_hermite_e")
 
 _lib = None
 
@@ -51,6 +52,16 @@ def lib() -> ctypes.CDLL:
         L.eri4_init.restype = c_int
         L.eri4_batch.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp]
         L.eri4_batch.restype = c_int
+        L.eri4_plan_create.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int]
+        L.eri4_plan_create.restype = c_int
+        L.eri4_plan_output_size.argtypes = [vp]
+        L.eri4_plan_output_size.restype = i64
+        L.eri4_plan_output_offsets.argtypes = [vp, vp]
+        L.eri4_plan_output_offsets.restype = c_int
+        L.eri4_plan_execute.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.eri4_plan_execute.restype = c_int
+        L.eri4_plan_destroy.argtypes = [vp]
+        L.eri4_plan_destroy.restype = c_int
         L.eri4_boys.argtypes = [c_int, i64, vp, vp, vp]
         L.eri4_boys.restype = c_int
         L.eri4_hermite_r.argtypes = [c_int, i64, vp, vp, vp, vp, vp, vp]
@@ -149,3 +160,55 @@ def hermite_e(la, lb, za, zb, A, B, E=None, stream=None):
     _check(lib().eri4_hermite_e(int(la), int(lb), n, _ptr(za, "float64"), _ptr(zb, "float64"),
                                 _ptr(A, "float64"), _ptr(B, "float64"), _ptr(E, "float64"), _stream(stream)))
     return E
+
+
+class Plan:
+    """A mixed-class batch computed by one persistent launch (eri4_plan_*).
+
+    lq, nprim: host int32 arrays [nq, 4] (angular momenta, contraction lengths).
+    """
+
+    def __init__(self, lq, nprim, kmax: int):
+        import numpy as np
+        self._lq = np.ascontiguousarray(lq, dtype=np.int32)
+        self._np = np.ascontiguousarray(nprim, dtype=np.int32)
+        assert self._lq.shape == self._np.shape and self._lq.ndim == 2 and self._lq.shape[1] == 4
+        self.nq = self._lq.shape[0]
+        self.kmax = int(kmax)
+        h = ctypes.c_void_p()
+        _check(lib().eri4_plan_create(ctypes.byref(h), self.nq, self._lq.ctypes.data_as(ctypes.c_void_p),
+                                      self._np.ctypes.data_as(ctypes.c_void_p), self.kmax))
+        self._h = h
+
+    @property
+    def output_size(self) -> int:
+        return lib().eri4_plan_output_size(self._h)
+
+    def offsets(self):
+        import numpy as np
+        off = np.zeros(self.nq, dtype=np.int64)
+        _check(lib().eri4_plan_output_offsets(self._h, off.ctypes.data_as(ctypes.c_void_p)))
+        return off
+
+    def execute(self, centers, exps, coefs, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.output_size, dtype=torch.float64, device=centers.device)
+        if out.numel() < self.output_size:
+            raise ValueError("output buffer too small")
+        if exps.shape[2] != self.kmax or centers.shape[0] != self.nq:
+            raise ValueError("inputs do not match the plan")
+        _check(lib().eri4_plan_execute(self._h, _ptr(centers, "float64"), _ptr(exps, "float64"),
+                                       _ptr(coefs, "float64"), _ptr(out, "float64"), _stream(stream)))
+        return out
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().eri4_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

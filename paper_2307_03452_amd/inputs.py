@@ -61,6 +61,22 @@ def normalize_shell(l: int, exps: np.ndarray, raw: np.ndarray) -> np.ndarray:
     return c / np.sqrt(tot)[..., None]
 
 
+def normalize_shells(l, exps, raw, nprim):
+    """Vectorised normalize_shell over [..., kmax] arrays with per-shell l and
+    contraction length; entries p >= nprim keep their raw value."""
+    l = np.asarray(l)
+    kmax = exps.shape[-1]
+    mask = np.arange(kmax) < np.asarray(nprim)[..., None]
+    df = np.vectorize(lambda n: _dfact(2 * int(n) - 1))(l).astype(np.float64)
+    lf = l.astype(np.float64)[..., None]
+    nrm = np.sqrt((4.0 * exps) ** lf * (2.0 * exps / np.pi) ** 1.5 / df[..., None])
+    c = np.where(mask, raw * nrm, 0.0)
+    zs = exps[..., :, None] + exps[..., None, :]
+    S = df[..., None, None] / (2.0 * zs) ** lf[..., None] * (np.pi / zs) ** 1.5
+    tot = np.einsum("...i,...ij,...j->...", c, S, c)
+    return np.where(mask, c / np.sqrt(tot)[..., None], raw)
+
+
 @dataclass
 class Batch:
     ls: tuple            # (la, lb, lc, ld) for single-class batches, else None
@@ -129,3 +145,31 @@ def iiii(K: int = 1, nq: int = 512, seed: int | None = None) -> Batch:
     if seed is None:
         seed = 1002 if K == 1 else 1003
     return class_batch((6, 6, 6, 6), nq, K, seed, exp_range=(0.05, 200.0))
+
+
+def zipf_classes(lvals=(4, 5, 6), s=1.2):
+    """Ordered classes (la lb|lc ld) over lvals^4, ranked by (total L, tuple),
+    with probabilities proportional to rank^-s."""
+    import itertools
+    cls = sorted(itertools.product(lvals, repeat=4), key=lambda t: (sum(t), t))
+    p = np.arange(1, len(cls) + 1, dtype=np.float64) ** -s
+    return cls, p / p.sum()
+
+
+def uneven_batch(nq: int = 20000, seed: int = 1004, lvals=(4, 5, 6), kmax: int = 8,
+                 exp_range=(0.05, 200.0), box: float = 8.0) -> Batch:
+    """Mixed batch: class counts multinomial over Zipf(1.2) ranked classes,
+    quartets shuffled, contraction length per shell uniform in 1..kmax."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cls, p = zipf_classes(lvals)
+    counts = rng.multinomial(nq, p)
+    lq = np.repeat(np.array(cls, dtype=np.int32), counts, axis=0)
+    lq = lq[rng.permutation(nq)]
+    nprim = rng.integers(1, kmax + 1, size=(nq, 4)).astype(np.int32)
+    centers = rng.uniform(0.0, box, size=(nq, 4, 3))
+    lo, hi = exp_range
+    exps = np.exp(rng.uniform(np.log(lo), np.log(hi), size=(nq, 4, kmax)))
+    raw = rng.uniform(0.1, 1.0, size=(nq, 4, kmax))
+    raw = np.where(nprim[..., None] == 1, 1.0, raw)
+    coefs = normalize_shells(lq, exps, raw, nprim)
+    return Batch(None, centers, exps, coefs, nprim, lq)

@@ -53,7 +53,7 @@ def test_batch_rejects_bad_arguments_on_host():
     L = eri4.lib()
     assert _batch(-1, 0, 0, 0, 1, 1) == STATUS_INVALID
     assert b"angular" in L.eri4_last_error()
-    assert _batch(7, 0, 0, 0, 1, 1) == STATUS_UNSUPPORTED
+    assert _batch(8, 0, 0, 0, 1, 1) == STATUS_UNSUPPORTED
     assert _batch(0, 0, 0, 0, -1, 1) == STATUS_INVALID
     assert _batch(0, 0, 0, 0, 1, 0) == STATUS_INVALID
     assert _batch(0, 0, 0, 0, 1, 17) == STATUS_INVALID
@@ -70,7 +70,7 @@ def test_stage_entry_points_reject_bad_arguments_on_host():
     assert L.eri4_boys(29, 1, n, n, None) == STATUS_INVALID
     assert L.eri4_boys(4, 3, n, n, None) == STATUS_INVALID
     assert L.eri4_boys(4, 0, n, n, None) == 0
-    assert L.eri4_hermite_r(25, 1, n, n, n, n, n, None) == STATUS_INVALID
+    assert L.eri4_hermite_r(29, 1, n, n, n, n, n, None) == STATUS_INVALID
     assert L.eri4_hermite_r(4, 1, n, n, n, n, n, None) == STATUS_INVALID
     assert L.eri4_hermite_e(8, 0, 1, n, n, n, n, n, None) == STATUS_INVALID
     assert L.eri4_hermite_e(2, 2, -1, n, n, n, n, n, None) == STATUS_INVALID
@@ -86,3 +86,45 @@ def test_errors_are_per_thread():
     t.join()
     assert seen == [b""]
     assert L.eri4_last_error() != b""
+
+
+def test_plan_create_rejects_bad_host_arrays_before_touching_a_device():
+    import numpy as np
+    L = eri4.lib()
+    h = ctypes.c_void_p()
+    lq = np.full((3, 4), 4, np.int32)
+    npr = np.ones((3, 4), np.int32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert L.eri4_plan_create(None, 3, ptr(lq), ptr(npr), 1) == STATUS_INVALID
+    assert L.eri4_plan_create(ctypes.byref(h), -1, ptr(lq), ptr(npr), 1) == STATUS_INVALID
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(lq), ptr(npr), 0) == STATUS_INVALID
+    assert L.eri4_plan_create(ctypes.byref(h), 3, None, ptr(npr), 1) == STATUS_INVALID
+    bad = lq.copy(); bad[2, 1] = 8
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(bad), ptr(npr), 1) == STATUS_UNSUPPORTED
+    bad[2, 1] = -1
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(bad), ptr(npr), 1) == STATUS_INVALID
+    badn = npr.copy(); badn[1, 3] = 2
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(lq), ptr(badn), 1) == STATUS_INVALID
+    assert b"contraction length" in L.eri4_last_error()
+    assert h.value is None
+    assert L.eri4_plan_output_size(None) == -1
+    assert L.eri4_plan_execute(None, None, None, None, None, None) == STATUS_INVALID
+    assert L.eri4_plan_destroy(None) == 0
+
+
+def test_uneven_batch_recipe():
+    import numpy as np
+    from paper_2307_03452_amd import inputs
+    cls, p = inputs.zipf_classes()
+    assert len(cls) == 81 and cls[0] == (4, 4, 4, 4) and cls[-1] == (6, 6, 6, 6)
+    assert abs(p[0] - 0.2843) < 1e-3 and abs(p.sum() - 1) < 1e-12
+    b = inputs.uneven_batch(nq=500, seed=3)
+    assert b.lq.shape == (500, 4) and b.nprim.min() >= 1 and b.nprim.max() <= 8
+    # every contracted shell's x^l component has unit norm (same check as the single-class generator)
+    for q in range(0, 500, 97):
+        for s in range(4):
+            k, l = int(b.nprim[q, s]), int(b.lq[q, s])
+            z = b.exps[q, s, :k]; c = b.coefs[q, s, :k]
+            zz = z[:, None] + z[None, :]
+            S = inputs._dfact(2 * l - 1) / (2 * zz) ** l * (np.pi / zz) ** 1.5
+            assert abs(c @ S @ c - 1.0) < 1e-12

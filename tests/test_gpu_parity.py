@@ -111,7 +111,7 @@ def _etab_magnitude(la, lb, za, zb, A, B, delta):
     return out
 
 
-@pytest.mark.parametrize("L", [0, 1, 2, 5, 12, 16, 20, 24])
+@pytest.mark.parametrize("L", [0, 1, 2, 5, 12, 16, 20, 24, 25, 26, 28])
 def test_hermite_r_stage(torch, L):
     rng = np.random.default_rng(L)
     n = 4
@@ -180,7 +180,8 @@ def test_gggg_uncontracted_64_quartets(torch):
     assert_quartets_close(g, o, label="gggg")
 
 
-@pytest.mark.parametrize("ls", [(4, 5, 6, 4), (6, 4, 5, 3), (0, 6, 6, 0), (6, 6, 0, 0), (3, 6, 2, 5), (5, 5, 5, 5)])
+@pytest.mark.parametrize("ls", [(4, 5, 6, 4), (6, 4, 5, 3), (0, 6, 6, 0), (6, 6, 0, 0), (3, 6, 2, 5), (5, 5, 5, 5),
+                                (7, 0, 0, 7), (7, 6, 5, 7), (6, 7, 6, 7), (7, 7, 6, 6), (7, 7, 7, 7)])
 def test_mixed_l_classes(torch, ls):
     b = inputs.class_batch(ls, 6, (1, 2), seed=sum(ls) * 7 + ls[0], exp_range=(0.05, 200.0), kmax=3)
     g = run_gpu(torch, b)
@@ -289,3 +290,11 @@ def test_bra_ket_swap_symmetry_at_full_size(torch):
     ht = np.transpose(h, (0, 3, 4, 1, 2))
     for q in range(b.nq):
         assert np.abs(g[q] - ht[q]).max() <= 2 * TOL * max(np.abs(g[q]).max(), ZERO_SCALE)
+
+
+def test_kkkk_contracted_k2(torch):
+    """(kk|kk), l = 7, K = 2 per shell (16-row tiles, slab layout of R)."""
+    b = inputs.class_batch((7, 7, 7, 7), 2, 2, seed=1005, exp_range=(0.05, 200.0))
+    g = run_gpu(torch, b)
+    o = oracle.eri_md4(b.ls, b.centers, b.exps, b.coefs, b.nprim)
+    assert_quartets_close(g, o, label="kkkk K2")
