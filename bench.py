@@ -95,13 +95,11 @@ def md4_flops_batch(lq, nprim):
     return tot
 
 
-def time_uneven(steps, warmup, nq=20000, seed=1004):
-    """Uneven batch in one persistent launch: all ordered classes in {4,5,6}^4,
-    Zipf(1.2) class counts, contraction length 1..8 per shell."""
+def time_plan(b, precision, steps, warmup):
+    """One plan over batch b (inputs resident in HBM): wall seconds per execute."""
     import torch
-    from paper_2307_03452_amd import eri4, inputs
-    b = inputs.uneven_batch(nq=nq, seed=seed)
-    plan = eri4.Plan(b.lq, b.nprim, b.kmax)
+    from paper_2307_03452_amd import eri4
+    plan = eri4.Plan(b.lq, b.nprim, b.kmax, precision=precision)
     d = lambda a: torch.from_numpy(a).cuda()
     C, E, Co = d(b.centers), d(b.exps), d(b.coefs)
     out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
@@ -112,14 +110,18 @@ def time_uneven(steps, warmup, nq=20000, seed=1004):
     for _ in range(steps):
         plan.execute(C, E, Co, out=out)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    flops = md4_flops_batch(b.lq, b.nprim)
-    # parity on a few sampled quartets (largest and random)
+    return plan, out, (time.perf_counter() - t0) / steps
+
+
+def sampled_oracle_err(b, plan, out, absolute=False):
+    """Largest error against the oracle over a few quartets of batch b (the one
+    with the largest total l and three random ones, among quartets whose four
+    contraction lengths multiply to at most 16, which the oracle does quickly):
+    relative to each quartet's largest integral, or absolute."""
     import numpy as np
     import oracle
+    from paper_2307_03452_amd import inputs
     off = plan.offsets()
-    # the oracle's cost grows with the product of the four contraction lengths:
-    # sample among quartets whose product is at most 16
     cheap = np.flatnonzero(np.prod(b.nprim, axis=1) <= 16)
     big = cheap[np.argmax(b.lq[cheap].sum(axis=1))]
     idx = sorted({int(big), *np.random.default_rng(7).choice(cheap, 3, replace=False).tolist()})
@@ -128,12 +130,70 @@ def time_uneven(steps, warmup, nq=20000, seed=1004):
         s_ = inputs.subset(b, [q])
         o = oracle.eri_md4(tuple(int(x) for x in b.lq[q]), s_.centers, s_.exps, s_.coefs, s_.nprim)[0]
         g = out[off[q]:off[q] + o.size].cpu().numpy().reshape(o.shape)
-        err = max(err, float(np.abs(g - o).max() / max(np.abs(o).max(), 1e-250)))
-    return {"workload": f"uneven batch: {nq} quartets, 81 classes (la lb|lc ld) in {{4,5,6}}^4 with Zipf(1.2) "
-                        "counts, K per shell uniform in 1..8, exponents [0.05,200], one persistent launch",
-            "value": plan.output_size / wall, "unit": "integrals/s", "ms_per_step": wall * 1e3,
-            "md4_tflops": flops / wall / 1e12, "pct_fp64_peak": 100 * flops / wall / 1e12 / FP64_PEAK_TFLOPS,
-            "parity_max_rel_err_sampled": err, "quartets": nq}
+        e = float(np.abs(g - o).max())
+        err = max(err, e if absolute else e / max(np.abs(o).max(), 1e-250))
+    return err
+
+
+UNEVEN_DESC = ("uneven batch: {nq} quartets, 81 classes (la lb|lc ld) in {{4,5,6}}^4 with Zipf(1.2) counts, "
+               "K per shell uniform in 1..8, exponents [0.05,200], one persistent launch")
+
+
+def time_uneven(steps, warmup, nq=20000, seed=1004, mixed_steps=0):
+    """Uneven batch in one persistent launch: all ordered classes in {4,5,6}^4,
+    Zipf(1.2) class counts, contraction length 1..8 per shell.  With
+    mixed_steps > 0 the same batch also runs with FP32 transforms."""
+    from paper_2307_03452_amd import inputs
+    b = inputs.uneven_batch(nq=nq, seed=seed)
+    plan, out, wall = time_plan(b, "fp64", steps, warmup)
+    flops = md4_flops_batch(b.lq, b.nprim)
+    rec = {"workload": UNEVEN_DESC.format(nq=nq),
+           "value": plan.output_size / wall, "unit": "integrals/s", "ms_per_step": wall * 1e3,
+           "md4_tflops": flops / wall / 1e12, "pct_fp64_peak": 100 * flops / wall / 1e12 / FP64_PEAK_TFLOPS,
+           "parity_max_rel_err_sampled": sampled_oracle_err(b, plan, out), "quartets": nq}
+    mixed = None
+    if mixed_steps > 0:
+        plan32, out32, wall32 = time_plan(b, "fp32", mixed_steps, 1)
+        mixed = {"workload": UNEVEN_DESC.format(nq=nq), "precision": "fp32",
+                 "transforms": "operands rounded to FP32, FP32 matrix cores, FP32 accumulation; "
+                               "Boys, R and E in FP64",
+                 "value": plan32.output_size / wall32, "unit": "integrals/s", "ms_per_step": wall32 * 1e3,
+                 "fp64_ms_per_step": wall * 1e3, "speedup_vs_fp64": wall / wall32,
+                 "oracle_max_abs_err_sampled": sampled_oracle_err(b, plan32, out32, absolute=True)}
+        mixed.update(class_errors(b, plan, out, out32))
+        del out32
+    return rec, mixed
+
+
+def class_errors(b, plan, ref, test, target=1e-10):
+    """Per class (la lb|lc ld): largest |test - ref| over all its quartets, with
+    ref the FP64 path (itself within 1e-12 of the oracle relative to each
+    quartet's largest integral), and the largest |ref|."""
+    import numpy as np
+    import torch
+    off = torch.from_numpy(plan.offsets()).cuda()
+    keys = [tuple(int(x) for x in r) for r in b.lq]
+    by_cls = {}
+    for q, k in enumerate(keys):
+        by_cls.setdefault(k, []).append(q)
+    per = []
+    for k, qs in sorted(by_cls.items()):
+        size = int(np.prod([(l + 1) * (l + 2) // 2 for l in k]))
+        ar = torch.arange(size, device="cuda")
+        err = mag = 0.0
+        step = max(1, (1 << 26) // size)
+        for i in range(0, len(qs), step):
+            idx = off[torch.tensor(qs[i:i + step], device="cuda")][:, None] + ar[None, :]
+            r = ref[idx]
+            err = max(err, float((test[idx] - r).abs().max()))
+            mag = max(mag, float(r.abs().max()))
+        per.append({"class": "(%d%d|%d%d)" % k, "quartets": len(qs), "max_abs_err": err, "max_abs_integral": mag})
+    worst = max(p["max_abs_err"] for p in per)
+    return {"max_abs_err": worst, "target_abs_err": target, "meets_target": worst <= target,
+            "classes_within_target": sum(p["max_abs_err"] <= target for p in per), "classes": len(per),
+            "error_reference": "FP64 path on the same inputs (all quartets)",
+            "worst_classes": sorted(per, key=lambda p: -p["max_abs_err"])[:5],
+            "per_class_max_abs_err": {p["class"]: p["max_abs_err"] for p in per}}
 
 
 def parity_sample(wl, b, out, n=2):
@@ -180,6 +240,8 @@ def main():
                     help="timed steps of the contracted (ii|ii) K=5 batch reported beside the headline (0: skip)")
     ap.add_argument("--uneven-steps", type=int, default=1,
                     help="timed steps of the 20k-quartet mixed-class batch reported beside the headline (0: skip)")
+    ap.add_argument("--mixed-steps", type=int, default=1,
+                    help="timed steps of the mixed-batch with FP32 transforms, compared with FP64 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -231,7 +293,9 @@ def main():
                             "unit": "integrals/s", "ms_per_step": wall5 * 1e3 / args.secondary_steps,
                             "md4_tflops": f5 / s5 / 1e12, "pct_fp64_peak": 100 * f5 / s5 / 1e12 / FP64_PEAK_TFLOPS}
     if args.uneven_steps > 0 and args.workload == "iiii_k1":
-        rec["uneven"] = time_uneven(args.uneven_steps, 1)
+        rec["uneven"], mixed = time_uneven(args.uneven_steps, 1, mixed_steps=args.mixed_steps)
+        if mixed is not None:
+            rec["mixed_precision"] = mixed
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

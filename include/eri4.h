@@ -50,6 +50,20 @@ typedef enum {
   ERI4_ERROR_INTERNAL = 5
 } eri4_status;
 
+/* Arithmetic of the two Hermite-to-Cartesian transforms of a plan.  Boys
+ * function, Hermite integrals and E coefficients are FP64 in both.
+ *   ERI4_PREC_FP64  FP64 matrix cores, FP64 accumulation (the paper's scheme).
+ *   ERI4_PREC_FP32  operands rounded to FP32 and multiplied on FP32 matrix
+ *                   cores with FP32 accumulation inside each transform (over the
+ *                   Hermite index and, for the bra transform, the bra primitive
+ *                   pairs); [ab|q] is held in FP64 between the transforms and the
+ *                   ket primitive pairs are summed into the FP64 output.  The
+ *                   error is that of FP32 arithmetic (unit roundoff 2^-24) times
+ *                   the magnitude of the terms summed, typically 1e-7 of a
+ *                   quartet's largest integral; it does not reach 1e-10
+ *                   absolute on quartets whose integrals exceed about 1e-3. */
+typedef enum { ERI4_PREC_FP64 = 0, ERI4_PREC_FP32 = 1 } eri4_precision;
+
 /* Largest angular momentum per shell accepted by eri4_batch. */
 #define ERI4_MAX_L 7
 /* Largest contraction length per shell (kmax) accepted by eri4_batch. */
@@ -115,6 +129,7 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets,
  * eri4_plan_create reads the HOST arrays
  *   l      int32 [nquartets][4]   angular momenta of shells a, b, c, d, 0..ERI4_MAX_L
  *   nprim  int32 [nquartets][4]   contraction lengths, 1..kmax
+ * and takes the arithmetic of the transforms (eri4_precision above),
  * splits every quartet into tiles of bra rows, orders the tiles by an estimate
  * of their cost (largest first) and uploads the schedule, the per-class
  * parameters, the output offsets and a copy of nprim to device memory that the
@@ -140,7 +155,7 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets,
 typedef struct eri4_plan_s* eri4_plan;
 
 eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
-                             int kmax);
+                             int kmax, eri4_precision precision);
 int64_t eri4_plan_output_size(eri4_plan plan);                         /* doubles; -1 if plan is NULL */
 eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets); /* HOST int64 [nquartets] */
 eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents,

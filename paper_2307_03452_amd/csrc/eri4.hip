@@ -39,6 +39,7 @@ void make_boys_table(std::vector<double>& tab);
 void make_rtabs(std::vector<uint32_t>& tab, std::vector<int>& start);
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxLdsBytes = 160 * 1024;
 
@@ -46,10 +47,35 @@ constexpr int kMaxLdsBytes = 160 * 1024;
 // device helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
-  // D[16x16] += A[16x4] B[4x16]; lane l holds A[l%16][l/16], B[l/16][l%16],
-  // and D rows 4j + l/16, column l%16 in element j.
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+// D[16x16] += A[16x4] B[4x16] on the matrix cores, in FP64 or (F32 = true)
+// with both operands rounded to FP32 and an FP32 accumulator.  Lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; element j of its accumulator is column l%16
+// of row acc_row<F32>(j, l/16).
+template <bool F32>
+struct Acc {
+  using type = d4;
+};
+template <>
+struct Acc<true> {
+  using type = f4;
+};
+
+template <bool F32>
+__device__ __forceinline__ typename Acc<F32>::type mfma16(double a, double b, typename Acc<F32>::type c) {
+  if constexpr (F32)
+    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <bool F32>
+__device__ __forceinline__ int acc_row(int j, int g) {
+  return F32 ? 4 * g + j : 4 * j + g;
+}
+
+template <bool F32>
+__device__ __forceinline__ typename Acc<F32>::type acc_zero() {
+  return typename Acc<F32>::type{0, 0, 0, 0};
 }
 
 // F_m(T), eq. (boys): Taylor expansion on the grid below kBoysTMax, asymptotic
@@ -203,6 +229,8 @@ __device__ __forceinline__ void load_rtab(uint2 (&ent)[NE], const uint2* __restr
 // Primitive-pair data, stored in LDS as 11 doubles:
 //   [0] z = za + zb, [1] w = ca cb exp(-za zb / z |A-B|^2) (Gaussian product
 //   prefactor times the two contraction coefficients), [2..4] P, [5..7] P-A, [8..10] P-B.
+// The ket pair's slots [11] and [12] hold the power-of-two scale of [0]^(m)
+// and its inverse (1 in FP64).
 constexpr int kPairDoubles = 11;
 
 __device__ __forceinline__ void make_pair(double* out, double za, double zb, double ca, double cb,
@@ -229,8 +257,8 @@ __device__ __forceinline__ void make_pair(double* out, double za, double zb, dou
 //   acc[r][c] += sum_p E_ab[row block r][p] * box[off(p) + off(q in block c)]
 // E_ab is the product of three bra-table entries.  All LDS reads of a k step
 // are issued before its MFMAs; the next p index is fetched one step ahead.
-template <int NR, int NC, bool SLAB>
-__device__ __forceinline__ void gemm1_pair(d4 (&acc)[NR][NC], const double* __restrict__ brae,
+template <int NR, int NC, bool SLAB, bool F32>
+__device__ __forceinline__ void gemm1_pair(typename Acc<F32>::type (&acc)[NR][NC], const double* __restrict__ brae,
                                            const double* __restrict__ R, const int2* __restrict__ ptab,
                                            const int (&rowx)[NR], const int (&rowy)[NR], const int (&rowz)[NR],
                                            const int (&offq)[NC], const int (&tq)[NC], int np4, int L, int S1,
@@ -260,7 +288,7 @@ __device__ __forceinline__ void gemm1_pair(d4 (&acc)[NR][NC], const double* __re
     for (int r = 0; r < NR; ++r) {
       const double a = ex[r] * ey[r] * ez[r];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[r][c] = mfma16(a, b[c], acc[r][c]);
+      for (int c = 0; c < NC; ++c) acc[r][c] = mfma16<F32>(a, b[c], acc[r][c]);
     }
   }
 }
@@ -269,10 +297,11 @@ __device__ __forceinline__ void gemm1_pair(d4 (&acc)[NR][NC], const double* __re
 // and NR row blocks, then the output write:
 //   out[ab][cd] (+)= sum_q X[ab][q] E_cd[cd][q]
 // E_cd is the product of three ket-table entries (sign of eq. (pq) folded in).
-template <int NR, int NC>
+template <int NR, int NC, bool F32>
 __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double* __restrict__ X,
                                             const double* __restrict__ kete, const int2* __restrict__ qtab,
-                                            int cb0, int row0, double* __restrict__ outq, bool first, int lane) {
+                                            int cb0, int row0, double* __restrict__ outq, bool first,
+                                            double unscale, int lane) {
   const int g = lane >> 4, n = lane & 15;
   int kx[NC], ky[NC], kz[NC];
 #pragma unroll
@@ -293,11 +322,11 @@ __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double*
       kz[c] = 2 * cp.tkaxis + zr;
     }
   }
-  d4 acc[NR][NC];
+  typename Acc<F32>::type acc[NR][NC];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < NC; ++c) acc[r][c] = acc_zero<F32>();
   const int xs = cp.xs, nq4 = cp.nq4;
   int pk = qtab[g].x;
   for (int kk = 0; kk < nq4; kk += 4) {
@@ -316,7 +345,7 @@ __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double*
     for (int c = 0; c < NC; ++c) {
       const double b = fx[c] * fy[c] * fz[c];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r][c] = mfma16(a[r], b, acc[r][c]);
+      for (int r = 0; r < NR; ++r) acc[r][c] = mfma16<F32>(a[r], b, acc[r][c]);
     }
   }
 #pragma unroll
@@ -326,13 +355,15 @@ __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double*
       const int cd = (cb0 + 8 * c) * 16 + n;
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const int ab = row0 + r * 16 + 4 * jj + g;
+        const int ab = row0 + r * 16 + acc_row<F32>(jj, g);
         if (ab < cp.nab && cd < cp.ncd) {
           double* o = outq + (int64_t)ab * cp.ncd + cd;
+          double v = acc[r][c][jj];
+          if constexpr (F32) v *= unscale;
           if (first)
-            __builtin_nontemporal_store(acc[r][c][jj], o);
+            __builtin_nontemporal_store(v, o);
           else
-            *o += acc[r][c][jj];
+            *o += v;
         }
       }
     }
@@ -348,7 +379,7 @@ constexpr int kGroup = 4;  // output column blocks per second-transform pass
 
 // Everything a workgroup does after its prologue, for NR valid row blocks and
 // NC1 first-transform column blocks of this wave.
-template <int NR, int NC1, bool SLAB>
+template <int NR, int NC1, bool SLAB, bool F32>
 __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, const double* __restrict__ boys_tab,
                            const uint2 (&rent)[SLAB ? kRPerThread : kRPerBox], double* __restrict__ outq,
                            int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane) {
@@ -397,12 +428,33 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
     if (tid == 0) {
       const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
       make_pair(s.kpair, ex[2 * kmax + k], ex[3 * kmax + l], co[2 * kmax + k], co[3 * kmax + l], C, D);
+      if constexpr (F32) {
+        // A power of two that brings the largest product of bra and ket pair
+        // weights near 1: [0]^(m) is multiplied by it so that the FP32
+        // operands of both transforms stay inside FP32's exponent range for
+        // quartets with tiny integrals; the output write divides it out.
+        double ab2 = 0.0;
+        for (int x = 0; x < 3; ++x) ab2 += (A[x] - B[x]) * (A[x] - B[x]);
+        double wmax = 0.0;
+        for (int ij = 0; ij < Ka * Kb; ++ij) {
+          const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
+          const double za = ex[i], zb = ex[kmax + j];
+          wmax = fmax(wmax, fabs(co[i] * co[kmax + j]) * exp(-za * zb / (za + zb) * ab2));
+        }
+        const double wq = wmax * fabs(s.kpair[1]);
+        const int e = (wq > 0.0 && wq < INFINITY) ? max(-1020, min(1020, ilogb(wq))) : 0;
+        s.kpair[11] = ldexp(1.0, -e);
+        s.kpair[12] = ldexp(1.0, e);
+      } else {
+        s.kpair[11] = 1.0;
+        s.kpair[12] = 1.0;
+      }
     }
-    d4 acc1[NR][NC1A];
+    typename Acc<F32>::type acc1[NR][NC1A];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int c = 0; c < NC1A; ++c) acc1[r][c] = (d4){0.0, 0.0, 0.0, 0.0};
+      for (int c = 0; c < NC1A; ++c) acc1[r][c] = acc_zero<F32>();
 
     for (int ij = 0; ij < Ka * Kb; ++ij) {
       if (tid == 64) {
@@ -425,7 +477,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
           const double F = boys_fm(lane, rho * r2, boys_tab);
           double pw = 1.0;
           for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
-          s.baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (s.bpair[1] * s.kpair[1]) * F;
+          s.baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (s.bpair[1] * (s.kpair[1] * s.kpair[11])) * F;
         }
       } else if (wave == 1) {
         build_etab(s.brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / s.bpair[0], s.bpair + 5, s.bpair + 8, false,
@@ -435,7 +487,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       hermite_r_lds(s.box, s.baseM, cp.L, s.pqv, rent, tid);
       // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
       if constexpr (NC1 > 0)
-        gemm1_pair<NR, NC1, SLAB>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, tq, cp.np4, cp.L, cp.S1, lane);
+        gemm1_pair<NR, NC1, SLAB, F32>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, tq, cp.np4, cp.L, cp.S1, lane);
       __syncthreads();
     }
 
@@ -448,7 +500,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
           const int cb = wave + 8 * c;
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj)
-            s.X[(r * 16 + 4 * jj + (lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = acc1[r][c][jj];
+            s.X[(r * 16 + acc_row<F32>(jj, lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = acc1[r][c][jj];
         }
     }
     if (wave == 0)
@@ -456,18 +508,19 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
     __syncthreads();
 
     // second transform, written to HBM (accumulated over kl)
+    const double unscale = s.kpair[12];
     for (int g0 = 0; g0 < ncbw; g0 += kGroup) {
       const int ng = min(kGroup, ncbw - g0);
       const int cb0 = wave + 8 * g0;
       const bool first = kl == 0;
       if (ng == 4)
-        gemm2_group<NR, 4>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, lane);
+        gemm2_group<NR, 4, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
       else if (ng == 3)
-        gemm2_group<NR, 3>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, lane);
+        gemm2_group<NR, 3, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
       else if (ng == 2)
-        gemm2_group<NR, 2>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, lane);
+        gemm2_group<NR, 2, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
       else
-        gemm2_group<NR, 1>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, lane);
+        gemm2_group<NR, 1, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
     }
     __syncthreads();
   }
@@ -475,7 +528,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
 
 // All the work of one tile: quartet q, bra rows rt*RB*16.., whose integrals
 // start at outq.  Called by every thread of the workgroup; ends with a barrier.
-template <int RB, bool SLAB>
+template <int RB, bool SLAB, bool F32>
 __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned char* lds,
                                              const double* __restrict__ boys_tab,
                                              const uint2* __restrict__ rtab_L,
@@ -524,7 +577,7 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
   }
   const int nc1 = (wave < cp.nqb) ? min(kMaxC1, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
   const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                             // valid row blocks of this tile
-#define BODY(NR, NC1) fused_body<NR, NC1, SLAB>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane)
+#define BODY(NR, NC1) fused_body<NR, NC1, SLAB, F32>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane)
   constexpr int NR2 = RB >= 2 ? 2 : 1;
   if (nrv == NR2 && NR2 == 2) {
     switch (nc1) {
@@ -569,7 +622,7 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
   const int64_t q = q0 + blockIdx.x / cp.nrt;
   const int rt = blockIdx.x % cp.nrt;
-  process_tile<RB, SLAB>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
+  process_tile<RB, SLAB, false>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
                          out + q * (int64_t)cp.nab * cp.ncd, q, rt, tid, wave, lane);
 }
 
@@ -577,7 +630,8 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
 // largest first, taken from a device counter until none are left (every
 // workgroup exits once the counter passes nitems).  qoff[q] is where quartet
 // q's integrals start in out.  Each class brings its own tile height and R
-// layout.
+// layout.  F32: both transforms on FP32 matrix cores (eri4_plan_create).
+template <bool F32>
 __global__ __launch_bounds__(kThreads, 1) void eri4_plan_kernel(
     const ClassParams* __restrict__ classes, const int2* __restrict__ items, int nitems,
     const int64_t* __restrict__ qoff, const int32_t* __restrict__ nprim, int* __restrict__ counter,
@@ -603,14 +657,14 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_plan_kernel(
     double* oq = out + qoff[q];
     if (cp.slab) {
       if (cp.rb == 2)
-        process_tile<2, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<2, true, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
       else
-        process_tile<1, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<1, true, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
     } else {
       if (cp.rb == 2)
-        process_tile<2, false>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<2, false, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
       else
-        process_tile<1, false>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<1, false, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
     }
   }
 }
@@ -744,7 +798,9 @@ eri4_status set_attrs() {
   if ((s = set_attr_one<2, false>()) != ERI4_SUCCESS) return s;
   if ((s = set_attr_one<1, true>()) != ERI4_SUCCESS) return s;
   if ((s = set_attr_one<2, true>()) != ERI4_SUCCESS) return s;
-  HIP_TRY(hipFuncSetAttribute((const void*)eri4_plan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+  HIP_TRY(hipFuncSetAttribute((const void*)eri4_plan_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxLdsBytes - 64));
+  HIP_TRY(hipFuncSetAttribute((const void*)eri4_plan_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLdsBytes - 64));
   HIP_TRY(hipFuncSetAttribute((const void*)hermite_r_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLdsBytes));
@@ -920,6 +976,7 @@ struct eri4_plan_s {
   int nclasses = 0;
   int lds_bytes = 0;
   int grid = 0;
+  bool f32 = false;  // ERI4_PREC_FP32
   int64_t out_size = 0;
   std::vector<int64_t> qoff;
   ClassParams* d_classes = nullptr;
@@ -939,10 +996,13 @@ static void plan_free(eri4_plan_s* p) {
   delete p;
 }
 
-eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim, int kmax) {
+eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim, int kmax,
+                             eri4_precision precision) {
   g_err.clear();
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
   *plan = nullptr;
+  if (precision != ERI4_PREC_FP64 && precision != ERI4_PREC_FP32)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "unknown precision %d", (int)precision);
   if (nquartets < 0 || nquartets > ((int64_t)1 << 31) - 1)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "nquartets must be in 0..2^31-1");
   if (kmax < 1 || kmax > ERI4_MAX_K)
@@ -965,6 +1025,7 @@ eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* 
   HIP_TRY(hipGetDevice(&p->device));
   p->nq = nquartets;
   p->kmax = kmax;
+  p->f32 = precision == ERI4_PREC_FP32;
 
   // classes present, keyed by (la,lb,lc,ld)
   std::vector<int> cls_of_key(8 * 8 * 8 * 8, -1);
@@ -1025,7 +1086,9 @@ eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* 
   int ncu = 0, per_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
   const hipError_t oe =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)eri4_plan_kernel, kThreads, p->lds_bytes);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, p->f32 ? (const void*)eri4_plan_kernel<true> : (const void*)eri4_plan_kernel<false>, kThreads,
+          p->lds_bytes);
   if (oe != hipSuccess || per_cu < 1) per_cu = 1;
   p->grid = (int)std::min<int64_t>(std::max(p->nitems, 1), (int64_t)ncu * per_cu);
 
@@ -1079,9 +1142,14 @@ eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const doubl
   if (st != ERI4_SUCCESS) return st;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, plan->d_counter);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(eri4_plan_kernel, dim3(plan->grid), dim3(kThreads), plan->lds_bytes, stream, plan->d_classes,
-                     plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter, d->boys, d->rtab,
-                     centers, exponents, coeffs, out);
+  if (plan->f32)
+    hipLaunchKernelGGL(eri4_plan_kernel<true>, dim3(plan->grid), dim3(kThreads), plan->lds_bytes, stream,
+                       plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter,
+                       d->boys, d->rtab, centers, exponents, coeffs, out);
+  else
+    hipLaunchKernelGGL(eri4_plan_kernel<false>, dim3(plan->grid), dim3(kThreads), plan->lds_bytes, stream,
+                       plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter,
+                       d->boys, d->rtab, centers, exponents, coeffs, out);
   HIP_TRY(hipGetLastError());
   return ERI4_SUCCESS;
 }

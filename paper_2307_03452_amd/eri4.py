@@ -17,6 +17,9 @@ ERI4_MAX_L = 7
 ERI4_MAX_K = 16
 ERI4_MAX_BOYS_M = 28
 
+# eri4_precision: arithmetic of the two transforms of a plan
+PRECISION = {"fp64": 0, "fp32": 1}
+
 STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UNSUPPORTED",
           3: "ERI4_ERROR_OUT_OF_MEMORY", 4: "ERI4_ERROR_HIP", 5: "ERI4_ERROR_INTERNAL"}
 
@@ -52,7 +55,7 @@ def lib() -> ctypes.CDLL:
         L.eri4_init.restype = c_int
         L.eri4_batch.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp]
         L.eri4_batch.restype = c_int
-        L.eri4_plan_create.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int]
+        L.eri4_plan_create.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int]
         L.eri4_plan_create.restype = c_int
         L.eri4_plan_output_size.argtypes = [vp]
         L.eri4_plan_output_size.restype = i64
@@ -166,18 +169,21 @@ class Plan:
     """A mixed-class batch computed by one persistent launch (eri4_plan_*).
 
     lq, nprim: host int32 arrays [nq, 4] (angular momenta, contraction lengths).
+    precision: "fp64" or "fp32", the arithmetic of the two transforms.
     """
 
-    def __init__(self, lq, nprim, kmax: int):
+    def __init__(self, lq, nprim, kmax: int, precision: str = "fp64"):
         import numpy as np
         self._lq = np.ascontiguousarray(lq, dtype=np.int32)
         self._np = np.ascontiguousarray(nprim, dtype=np.int32)
         assert self._lq.shape == self._np.shape and self._lq.ndim == 2 and self._lq.shape[1] == 4
         self.nq = self._lq.shape[0]
         self.kmax = int(kmax)
+        self.precision = precision
         h = ctypes.c_void_p()
         _check(lib().eri4_plan_create(ctypes.byref(h), self.nq, self._lq.ctypes.data_as(ctypes.c_void_p),
-                                      self._np.ctypes.data_as(ctypes.c_void_p), self.kmax))
+                                      self._np.ctypes.data_as(ctypes.c_void_p), self.kmax,
+                                      PRECISION[precision] if isinstance(precision, str) else int(precision)))
         self._h = h
 
     @property

@@ -95,17 +95,19 @@ def test_plan_create_rejects_bad_host_arrays_before_touching_a_device():
     lq = np.full((3, 4), 4, np.int32)
     npr = np.ones((3, 4), np.int32)
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    assert L.eri4_plan_create(None, 3, ptr(lq), ptr(npr), 1) == STATUS_INVALID
-    assert L.eri4_plan_create(ctypes.byref(h), -1, ptr(lq), ptr(npr), 1) == STATUS_INVALID
-    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(lq), ptr(npr), 0) == STATUS_INVALID
-    assert L.eri4_plan_create(ctypes.byref(h), 3, None, ptr(npr), 1) == STATUS_INVALID
+    assert L.eri4_plan_create(None, 3, ptr(lq), ptr(npr), 1, 0) == STATUS_INVALID
+    assert L.eri4_plan_create(ctypes.byref(h), -1, ptr(lq), ptr(npr), 1, 0) == STATUS_INVALID
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(lq), ptr(npr), 0, 0) == STATUS_INVALID
+    assert L.eri4_plan_create(ctypes.byref(h), 3, None, ptr(npr), 1, 0) == STATUS_INVALID
     bad = lq.copy(); bad[2, 1] = 8
-    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(bad), ptr(npr), 1) == STATUS_UNSUPPORTED
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(bad), ptr(npr), 1, 0) == STATUS_UNSUPPORTED
     bad[2, 1] = -1
-    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(bad), ptr(npr), 1) == STATUS_INVALID
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(bad), ptr(npr), 1, 0) == STATUS_INVALID
     badn = npr.copy(); badn[1, 3] = 2
-    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(lq), ptr(badn), 1) == STATUS_INVALID
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(lq), ptr(badn), 1, 0) == STATUS_INVALID
     assert b"contraction length" in L.eri4_last_error()
+    assert L.eri4_plan_create(ctypes.byref(h), 3, ptr(lq), ptr(npr), 1, 7) == STATUS_INVALID
+    assert b"precision" in L.eri4_last_error()
     assert h.value is None
     assert L.eri4_plan_output_size(None) == -1
     assert L.eri4_plan_execute(None, None, None, None, None, None) == STATUS_INVALID
