@@ -1,4 +1,7 @@
-"""Build liberi4.so (the gfx950 HIP library) in-tree with hipcc."""
+"""Build liberi4.so (the gfx950 HIP library) in-tree with hipcc.
+
+Each translation unit is compiled on its own, in parallel (the two plan
+kernels and the fused kernels are the long ones), then linked."""
 import os
 import subprocess
 import sys
@@ -7,10 +10,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liberi4.so")
-SOURCES = ["eri4.hip", "eri4_tables.cpp"]
+OBJDIR = os.path.join(HERE, "_build")
+SOURCES = ["eri4_plan64.hip", "eri4_plan32.hip", "eri4_fused.hip", "eri4.hip", "eri4_tables.cpp"]
+HEADERS = ["eri4_device.h", "eri4_internal.h", "eri4_launch.h"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -19,8 +24,19 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc, *HIPCC_FLAGS, "-I" + INC, "-I" + CSRC, "-o", LIB + ".tmp", *srcs]
+    os.makedirs(OBJDIR, exist_ok=True)
+    procs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc, *HIPCC_FLAGS, "-I" + INC, "-I" + CSRC, "-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd)))
+        objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

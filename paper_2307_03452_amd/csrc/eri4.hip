@@ -1,23 +1,9 @@
-// eri4.hip -- gfx950 kernels and the C ABI of liberi4.
+// eri4.hip -- host side of liberi4's C ABI (gfx950), and the small stage
+// kernels.  The fused and plan kernels live in eri4_device.h and are compiled
+// in eri4_fused.hip, eri4_plan64.hip and eri4_plan32.hip.
 //
 // (ab|cd) over contracted Cartesian Gaussians by the matrix form of the
-// McMurchie-Davidson scheme (Asadchev & Valeev, Sec. 2 and Sec. 3):
-//
-//   [0]^(m) = (-2 rho)^m 2 pi^(5/2) / (zp zq sqrt(zp+zq)) F_m(rho |P-Q|^2)
-//   [r + 1_i]^(m) = r_i [r - 1_i]^(m+1) + (P_i - Q_i) [r]^(m+1)      eq. (md1)
-//   [p|q] = (-1)^|q| [p+q]^(0)                                       eq. (pq)
-//   [ab|q] = sum_p E_ab^p [p|q]                                      eq. (ab_to_hermite)
-//   (ab|cd) = sum_q E_cd^q [ab|q]                                    eq. (cd_to_hermite)
-//
-// One workgroup (8 waves) owns one quartet and a tile of RB*16 bra rows ab.
-// For each ket primitive pair kl it accumulates, over the bra primitive pairs
-// ij, the first transform [ab_tile|q] in FP64 MFMA registers (the contraction
-// is folded into the product dimension, Sec. 3), moves that tile to LDS and
-// applies the second transform straight into the output.  [p|q] is never
-// stored: its entries are gathered from the R box in LDS, whose linear layout
-// turns the index p+q into an address sum.  E entries are products of three
-// 1-d tables in LDS.  The sign (-1)^|q| is folded into the ket tables and the
-// Gaussian-product prefactors and contraction coefficients into [0]^(m).
+// McMurchie-Davidson scheme (Asadchev & Valeev, Sec. 2 and Sec. 3).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,642 +18,13 @@
 #include <vector>
 
 #include "eri4.h"
+#include "eri4_device.h"
 #include "eri4_internal.h"
+#include "eri4_launch.h"
 
 namespace eri4 {
 void make_boys_table(std::vector<double>& tab);
 void make_rtabs(std::vector<uint32_t>& tab, std::vector<int>& start);
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-constexpr int kMaxLdsBytes = 160 * 1024;
-
-// ---------------------------------------------------------------------------
-// device helpers
-// ---------------------------------------------------------------------------
-
-// D[16x16] += A[16x4] B[4x16] on the matrix cores, in FP64 or (F32 = true)
-// with both operands rounded to FP32 and an FP32 accumulator.  Lane l holds
-// A[l%16][l/16] and B[l/16][l%16]; element j of its accumulator is column l%16
-// of row acc_row<F32>(j, l/16).
-template <bool F32>
-struct Acc {
-  using type = d4;
-};
-template <>
-struct Acc<true> {
-  using type = f4;
-};
-
-template <bool F32>
-__device__ __forceinline__ typename Acc<F32>::type mfma16(double a, double b, typename Acc<F32>::type c) {
-  if constexpr (F32)
-    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
-  else
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-template <bool F32>
-__device__ __forceinline__ int acc_row(int j, int g) {
-  return F32 ? 4 * g + j : 4 * j + g;
-}
-
-template <bool F32>
-__device__ __forceinline__ typename Acc<F32>::type acc_zero() {
-  return typename Acc<F32>::type{0, 0, 0, 0};
-}
-
-// F_m(T), eq. (boys): Taylor expansion on the grid below kBoysTMax, asymptotic
-// form above.  Negative T gives NaN.
-__device__ double boys_fm(int m, double T, const double* __restrict__ tab) {
-  if (T >= 0.0 && T < kBoysTMax) {
-    const int i = (int)(T * kBoysInvH + 0.5);
-    const double x = (double)i * kBoysH - T;  // -(T - T_i), exact
-    const double* r = tab + (size_t)i * kBoysCols + m;
-    double s = r[kBoysJ];
-#pragma unroll
-    for (int j = kBoysJ - 1; j >= 0; --j) s = fma(s * x, 1.0 / (double)(j + 1), r[j]);
-    return s;
-  }
-  if (!(T >= 0.0)) return __builtin_nan("");
-  // F_m(T) = Gamma(m+1/2) / (2 T^(m+1/2)); the neglected incomplete-gamma part
-  // is below 1e-20 relative for T >= kBoysTMax and m <= kMaxL.
-  return tab[(size_t)kBoysAsymRow * kBoysCols + m] / (pow(T, (double)m) * sqrt(T));
-}
-
-// One step of the E recursions that follow eq. (cart2herm-2):
-//   E^t <- (1/(2 zp)) E^(t-1) + c E^t + (t+1) E^(t+1),  c = P-A or P-B.
-__device__ __forceinline__ void etab_step(double (&e)[16], double h, double c) {
-  double prev = 0.0;
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const double cur = e[t];
-    const double nxt = (t + 1 < 16) ? e[t + 1] : 0.0;
-    e[t] = h * prev + c * cur + (double)(t + 1) * nxt;
-    prev = cur;
-  }
-}
-
-// Three 1-d tables (x, y, z) of one primitive pair into LDS, one wave:
-// row (a,b) of axis i at E + i*taxis + (a*(lb+1)+b)*trow, entries t < trow
-// (t > a+b are 0, in particular the last one).  Each axis ends with an all-zero
-// row at row index (la+1)*(lb+1), used for padding rows.  alt_sign multiplies
-// entry t by (-1)^t (the ket side of eq. (pq)).
-__device__ void build_etab(double* E, int la, int lb, int trow, int taxis, double h,
-                           const double* PA, const double* PB, bool alt_sign, int lane) {
-  const int na = la + 1;
-  for (int j = lane; j < 3 * trow; j += 64) {  // the all-zero padding rows
-    const int axis = j / trow;
-    E[axis * taxis + na * (lb + 1) * trow + (j - axis * trow)] = 0.0;
-  }
-  if (lane < 3 * na) {
-    const int axis = lane / na;
-    const int a = lane - axis * na;
-    const double pa = PA[axis], pb = PB[axis];
-    double e[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) e[t] = (t == 0) ? 1.0 : 0.0;
-    for (int s = 0; s < a; ++s) etab_step(e, h, pa);
-    double* base = E + axis * taxis + a * (lb + 1) * trow;
-    for (int b = 0; b <= lb; ++b) {
-      double* row = base + b * trow;
-#pragma unroll
-      for (int t = 0; t < 16; ++t)
-        if (t < trow) row[t] = (alt_sign && (t & 1)) ? -e[t] : e[t];
-      for (int t = 16; t < trow; ++t) row[t] = 0.0;  // beyond a+b <= 14
-      if (b < lb) etab_step(e, h, pb);
-    }
-  }
-}
-
-// Hermite index table: ordinal -> (t,u,v) in lexicographic order over
-// t+u+v <= Lh, packed t | u<<8 | v<<16 | t<<24 together with its part of the R
-// offset (box: t*S2 + u*S1 + v; slab: u*S1 + v, the slab of the summed t,
-// taken from bits 24.., is added per gather).  Entries n..n_alloc-1 are
-// padding: E index (Lh+1, 0, 0), whose value is 0, and R index (0,0,0).
-__device__ void build_htab(int2* tab, int Lh, int n, int n_alloc, int S1, int S2, bool slab, int tid) {
-  const int ncol = (Lh + 1) * (Lh + 2) / 2;
-  for (int c = tid; c < ncol; c += kThreads) {
-    int t = 0, rem = c;
-    while (rem >= Lh - t + 1) {
-      rem -= Lh - t + 1;
-      ++t;
-    }
-    const int u = rem;
-    // triples before column (t,u): all with a smaller t, then columns u' < u of this t
-    const int first = (nherm(Lh) - nherm(Lh - t)) + u * (2 * (Lh - t) + 3 - u) / 2;
-    for (int v = 0; v <= Lh - t - u; ++v)
-      tab[first + v] = make_int2(t | (u << 8) | (v << 16) | (t << 24), (slab ? 0 : t * S2) + u * S1 + v);
-  }
-  for (int i = n + tid; i < n_alloc; i += kThreads) tab[i] = make_int2(Lh + 1, 0);
-}
-
-// Cartesian component index -> (x, y, z) for shell l (order ax = l..0, ay = l-ax..0).
-__device__ __forceinline__ void cart_of(int l, int i, int& x, int& y, int& z) {
-  int n = 0;
-  while ((n + 1) * (n + 2) / 2 <= i) ++n;
-  z = i - n * (n + 1) / 2;
-  y = n - z;
-  x = l - n;
-}
-
-// [r]^(0) for |r| <= L in LDS (box or slab layout, encoded in the table), by
-// eq. (md1) for decreasing m, overwriting [r]^(m+1) with [r]^(m).  Each level
-// reads all its operands into registers, then writes after a barrier.
-// baseM[m] holds [0]^(m); PQ (3 doubles, LDS) is P - Q.  ent[] holds this
-// thread's recursion-table entries; they are made opaque every level so that
-// only the packed words stay live, not their decoded form.
-template <int NE>
-__device__ void hermite_r_lds(double* R, const double* baseM, int L, const double* PQ, const uint2 (&ent_in)[NE],
-                              int tid) {
-  uint2 ent[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) ent[k] = ent_in[k];
-  if (tid == 0) R[0] = baseM[L];
-  __syncthreads();
-  const double px = PQ[0], py = PQ[1], pz = PQ[2];
-  for (int m = L - 1; m >= 0; --m) {
-    const int nact = nherm(L - m);
-    const int kact = (nact + kThreads - 1) / kThreads;  // entry slots in use at this level (uniform)
-    double nv[NE];
-#pragma unroll
-    for (int k = 0; k < NE; ++k) {
-      if (k < kact) {
-        asm volatile("" : "+v"(ent[k].x), "+v"(ent[k].y));
-        const int o1 = (int)(ent[k].x >> 16);
-        const int o2 = (int)(ent[k].y & 0xffffu);
-        const int dir = (int)((ent[k].y >> 16) & 3u);
-        const int ri = (int)(ent[k].y >> 18);
-        const double c1 = dir == 0 ? px : (dir == 1 ? py : pz);
-        nv[k] = c1 * R[o1] + (double)max(ri - 1, 0) * R[o2];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NE; ++k) {
-      if (k < kact) {
-        const int e = tid + k * kThreads;
-        if (e < nact && e > 0) R[ent[k].x & 0xffffu] = nv[k];
-      }
-    }
-    if (tid == 0) R[0] = baseM[m];
-    __syncthreads();
-  }
-}
-
-template <int NE>
-__device__ __forceinline__ void load_rtab(uint2 (&ent)[NE], const uint2* __restrict__ rt, int L, int tid) {
-  const int n = nherm(L);
-#pragma unroll
-  for (int k = 0; k < NE; ++k) {
-    const int e = tid + k * kThreads;
-    ent[k] = (e < n) ? rt[e] : make_uint2(0u, 0u);
-  }
-}
-
-// Primitive-pair data, stored in LDS as 11 doubles:
-//   [0] z = za + zb, [1] w = ca cb exp(-za zb / z |A-B|^2) (Gaussian product
-//   prefactor times the two contraction coefficients), [2..4] P, [5..7] P-A, [8..10] P-B.
-// The ket pair's slots [11] and [12] hold the power-of-two scale of [0]^(m)
-// and its inverse (1 in FP64).
-constexpr int kPairDoubles = 11;
-
-__device__ __forceinline__ void make_pair(double* out, double za, double zb, double ca, double cb,
-                                          const double* A, const double* B) {
-  const double z = za + zb;
-  const double iz = 1.0 / z;
-  double ab2 = 0.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    // P - A = zb (B - A) / z and P - B = za (A - B) / z, formed without the
-    // cancellation of subtracting two absolute positions
-    const double dd = A[i] - B[i];
-    out[2 + i] = (za * A[i] + zb * B[i]) * iz;
-    out[5 + i] = -zb * iz * dd;
-    out[8 + i] = za * iz * dd;
-    ab2 += dd * dd;
-  }
-  out[0] = z;
-  out[1] = ca * cb * exp(-za * zb * iz * ab2);
-}
-
-// First transform over one bra primitive pair for NR row blocks x NC column
-// blocks of this wave (both fixed per wave):
-//   acc[r][c] += sum_p E_ab[row block r][p] * box[off(p) + off(q in block c)]
-// E_ab is the product of three bra-table entries.  All LDS reads of a k step
-// are issued before its MFMAs; the next p index is fetched one step ahead.
-template <int NR, int NC, bool SLAB, bool F32>
-__device__ __forceinline__ void gemm1_pair(typename Acc<F32>::type (&acc)[NR][NC], const double* __restrict__ brae,
-                                           const double* __restrict__ R, const int2* __restrict__ ptab,
-                                           const int (&rowx)[NR], const int (&rowy)[NR], const int (&rowz)[NR],
-                                           const int (&offq)[NC], const int (&tq)[NC], int np4, int L, int S1,
-                                           int lane) {
-  const int g = lane >> 4;
-  int2 pt = ptab[g];
-  for (int kk = 0; kk < np4; kk += 4) {
-    const int tp = pt.x & 0xff, up = (pt.x >> 8) & 0xff, vp = (pt.x >> 16) & 0xff;
-    double ex[NR], ey[NR], ez[NR], b[NC];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      ex[r] = brae[rowx[r] + tp];
-      ey[r] = brae[rowy[r] + up];
-      ez[r] = brae[rowz[r] + vp];
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if constexpr (SLAB) {
-        const int t = (pt.x >> 24) + tq[c];  // t of p+q selects the slab
-        b[c] = R[slab_base(t, L, S1) + pt.y + offq[c]];
-      } else {
-        b[c] = R[pt.y + offq[c]];
-      }
-    }
-    pt = ptab[min(kk + 4, np4 - 4) + g];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double a = ex[r] * ey[r] * ez[r];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) acc[r][c] = mfma16<F32>(a, b[c], acc[r][c]);
-    }
-  }
-}
-
-// Second transform for one group of NC output column blocks (cb0, cb0+8, ...)
-// and NR row blocks, then the output write:
-//   out[ab][cd] (+)= sum_q X[ab][q] E_cd[cd][q]
-// E_cd is the product of three ket-table entries (sign of eq. (pq) folded in).
-template <int NR, int NC, bool F32>
-__device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double* __restrict__ X,
-                                            const double* __restrict__ kete, const int2* __restrict__ qtab,
-                                            int cb0, int row0, double* __restrict__ outq, bool first,
-                                            double unscale, int lane) {
-  const int g = lane >> 4, n = lane & 15;
-  int kx[NC], ky[NC], kz[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const int cd = (cb0 + 8 * c) * 16 + n;
-    if (cd < cp.ncd) {
-      const int ic = cd / cp.nd, id = cd - (cd / cp.nd) * cp.nd;
-      int cx, cy, cz, dx, dy, dz;
-      cart_of(cp.lc, ic, cx, cy, cz);
-      cart_of(cp.ld, id, dx, dy, dz);
-      kx[c] = (cx * (cp.ld + 1) + dx) * cp.tkrow;
-      ky[c] = cp.tkaxis + (cy * (cp.ld + 1) + dy) * cp.tkrow;
-      kz[c] = 2 * cp.tkaxis + (cz * (cp.ld + 1) + dz) * cp.tkrow;
-    } else {
-      const int zr = (cp.lc + 1) * (cp.ld + 1) * cp.tkrow;
-      kx[c] = zr;
-      ky[c] = cp.tkaxis + zr;
-      kz[c] = 2 * cp.tkaxis + zr;
-    }
-  }
-  typename Acc<F32>::type acc[NR][NC];
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[r][c] = acc_zero<F32>();
-  const int xs = cp.xs, nq4 = cp.nq4;
-  int pk = qtab[g].x;
-  for (int kk = 0; kk < nq4; kk += 4) {
-    const int tq = pk & 0xff, uq = (pk >> 8) & 0xff, vq = (pk >> 16) & 0xff;
-    double a[NR], fx[NC], fy[NC], fz[NC];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) a[r] = X[(r * 16 + n) * xs + kk + g];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      fx[c] = kete[kx[c] + tq];
-      fy[c] = kete[ky[c] + uq];
-      fz[c] = kete[kz[c] + vq];
-    }
-    pk = qtab[min(kk + 4, nq4 - 4) + g].x;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const double b = fx[c] * fy[c] * fz[c];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r][c] = mfma16<F32>(a[r], b, acc[r][c]);
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int cd = (cb0 + 8 * c) * 16 + n;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int ab = row0 + r * 16 + acc_row<F32>(jj, g);
-        if (ab < cp.nab && cd < cp.ncd) {
-          double* o = outq + (int64_t)ab * cp.ncd + cd;
-          double v = acc[r][c][jj];
-          if constexpr (F32) v *= unscale;
-          if (first)
-            __builtin_nontemporal_store(v, o);
-          else
-            *o += v;
-        }
-      }
-    }
-}
-
-// LDS regions of the fused kernel (see make_params for the layout).
-struct Lds {
-  double *sh, *baseM, *kpair, *bpair, *pqv, *box, *brae, *X, *kete;
-  int2 *ptab, *qtab;
-};
-
-constexpr int kGroup = 4;  // output column blocks per second-transform pass
-
-// Everything a workgroup does after its prologue, for NR valid row blocks and
-// NC1 first-transform column blocks of this wave.
-template <int NR, int NC1, bool SLAB, bool F32>
-__device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, const double* __restrict__ boys_tab,
-                           const uint2 (&rent)[SLAB ? kRPerThread : kRPerBox], double* __restrict__ outq,
-                           int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane) {
-  const int kmax = cp.kmax;
-  const double* A = s.sh;
-  const double* B = s.sh + 3;
-  const double* C = s.sh + 6;
-  const double* D = s.sh + 9;
-  const double* ex = s.sh + 12;
-  const double* co = s.sh + 12 + 4 * kmax;
-  constexpr int NC1A = NC1 > 0 ? NC1 : 1;
-
-  // bra rows of this lane (A operand of the first transform)
-  int rowx[NR], rowy[NR], rowz[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int ab = row0 + r * 16 + (lane & 15);
-    if (ab < cp.nab) {
-      const int ia = ab / cp.nb, ib = ab - ia * cp.nb;
-      int ax, ay, az, bx, by, bz;
-      cart_of(cp.la, ia, ax, ay, az);
-      cart_of(cp.lb, ib, bx, by, bz);
-      rowx[r] = (ax * (cp.lb + 1) + bx) * cp.tbrow;
-      rowy[r] = cp.tbaxis + (ay * (cp.lb + 1) + by) * cp.tbrow;
-      rowz[r] = 2 * cp.tbaxis + (az * (cp.lb + 1) + bz) * cp.tbrow;
-    } else {
-      const int zr = (cp.la + 1) * (cp.lb + 1) * cp.tbrow;
-      rowx[r] = zr;
-      rowy[r] = cp.tbaxis + zr;
-      rowz[r] = 2 * cp.tbaxis + zr;
-    }
-  }
-  // [ab|q] columns of this lane (B operand of the first transform)
-  int offq[NC1A], tq[NC1A];
-#pragma unroll
-  for (int c = 0; c < NC1A; ++c) {
-    const int2 e = (c < NC1) ? s.qtab[(wave + 8 * c) * 16 + (lane & 15)] : make_int2(0, 0);
-    offq[c] = e.y;
-    tq[c] = (int)((unsigned)e.x >> 24);
-  }
-  const int ncbw = (wave < cp.ncdb) ? (cp.ncdb - wave + 7) / 8 : 0;  // output column blocks of this wave
-
-  const double pref = 2.0 * pow(M_PI, 2.5);
-
-  for (int kl = 0; kl < Kc * Kd; ++kl) {
-    if (tid == 0) {
-      const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
-      make_pair(s.kpair, ex[2 * kmax + k], ex[3 * kmax + l], co[2 * kmax + k], co[3 * kmax + l], C, D);
-      if constexpr (F32) {
-        // A power of two that brings the largest product of bra and ket pair
-        // weights near 1: [0]^(m) is multiplied by it so that the FP32
-        // operands of both transforms stay inside FP32's exponent range for
-        // quartets with tiny integrals; the output write divides it out.
-        double ab2 = 0.0;
-        for (int x = 0; x < 3; ++x) ab2 += (A[x] - B[x]) * (A[x] - B[x]);
-        double wmax = 0.0;
-        for (int ij = 0; ij < Ka * Kb; ++ij) {
-          const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
-          const double za = ex[i], zb = ex[kmax + j];
-          wmax = fmax(wmax, fabs(co[i] * co[kmax + j]) * exp(-za * zb / (za + zb) * ab2));
-        }
-        const double wq = wmax * fabs(s.kpair[1]);
-        const int e = (wq > 0.0 && wq < INFINITY) ? max(-1020, min(1020, ilogb(wq))) : 0;
-        s.kpair[11] = ldexp(1.0, -e);
-        s.kpair[12] = ldexp(1.0, e);
-      } else {
-        s.kpair[11] = 1.0;
-        s.kpair[12] = 1.0;
-      }
-    }
-    typename Acc<F32>::type acc1[NR][NC1A];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int c = 0; c < NC1A; ++c) acc1[r][c] = acc_zero<F32>();
-
-    for (int ij = 0; ij < Ka * Kb; ++ij) {
-      if (tid == 64) {
-        const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
-        make_pair(s.bpair, ex[i], ex[kmax + j], co[i], co[kmax + j], A, B);
-      }
-      __syncthreads();
-      if (wave == 0) {
-        if (lane < 3) s.pqv[lane] = s.bpair[2 + lane] - s.kpair[2 + lane];
-        if (lane <= cp.L) {
-          const double zp = s.bpair[0], zq = s.kpair[0];
-          const double zs = zp + zq;
-          const double rho = zp * zq / zs;
-          double r2 = 0.0;
-#pragma unroll
-          for (int x = 0; x < 3; ++x) {
-            const double d = s.bpair[2 + x] - s.kpair[2 + x];
-            r2 += d * d;
-          }
-          const double F = boys_fm(lane, rho * r2, boys_tab);
-          double pw = 1.0;
-          for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
-          s.baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (s.bpair[1] * (s.kpair[1] * s.kpair[11])) * F;
-        }
-      } else if (wave == 1) {
-        build_etab(s.brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / s.bpair[0], s.bpair + 5, s.bpair + 8, false,
-                   lane);
-      }
-      __syncthreads();
-      hermite_r_lds(s.box, s.baseM, cp.L, s.pqv, rent, tid);
-      // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
-      if constexpr (NC1 > 0)
-        gemm1_pair<NR, NC1, SLAB, F32>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, tq, cp.np4, cp.L, cp.S1, lane);
-      __syncthreads();
-    }
-
-    // [ab_tile|q] -> LDS (aliases the R box); ket tables for kl
-    if constexpr (NC1 > 0) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int c = 0; c < NC1; ++c) {
-          const int cb = wave + 8 * c;
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj)
-            s.X[(r * 16 + acc_row<F32>(jj, lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = acc1[r][c][jj];
-        }
-    }
-    if (wave == 0)
-      build_etab(s.kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / s.kpair[0], s.kpair + 5, s.kpair + 8, true, lane);
-    __syncthreads();
-
-    // second transform, written to HBM (accumulated over kl)
-    const double unscale = s.kpair[12];
-    for (int g0 = 0; g0 < ncbw; g0 += kGroup) {
-      const int ng = min(kGroup, ncbw - g0);
-      const int cb0 = wave + 8 * g0;
-      const bool first = kl == 0;
-      if (ng == 4)
-        gemm2_group<NR, 4, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
-      else if (ng == 3)
-        gemm2_group<NR, 3, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
-      else if (ng == 2)
-        gemm2_group<NR, 2, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
-      else
-        gemm2_group<NR, 1, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
-    }
-    __syncthreads();
-  }
-}
-
-// All the work of one tile: quartet q, bra rows rt*RB*16.., whose integrals
-// start at outq.  Called by every thread of the workgroup; ends with a barrier.
-template <int RB, bool SLAB, bool F32>
-__device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned char* lds,
-                                             const double* __restrict__ boys_tab,
-                                             const uint2* __restrict__ rtab_L,
-                                             const double* __restrict__ centers, const double* __restrict__ exps,
-                                             const double* __restrict__ coefs, const int32_t* __restrict__ nprim,
-                                             double* __restrict__ outq, int64_t q, int rt, int tid, int wave,
-                                             int lane) {
-  const int kmax = cp.kmax;
-  Lds s;
-  s.sh = (double*)(lds + cp.o_shell);
-  s.baseM = (double*)(lds + cp.o_base);
-  s.kpair = s.baseM + 32;
-  s.bpair = s.kpair + 16;
-  s.pqv = s.bpair + 16;
-  s.ptab = (int2*)(lds + cp.o_ptab);
-  s.qtab = (int2*)(lds + cp.o_qtab);
-  s.box = (double*)(lds + cp.o_union);
-  s.brae = (double*)(lds + cp.o_brae);
-  s.X = (double*)(lds + cp.o_union);
-  s.kete = (double*)(lds + cp.o_kete);
-  int* shn = (int*)(s.sh + 12 + 8 * kmax);
-
-  // shell data of this quartet
-  if (tid < 12) {
-    s.sh[tid] = centers[q * 12 + tid];
-  } else if (tid < 12 + 8 * kmax) {
-    const int j = tid - 12;
-    s.sh[tid] = (j < 4 * kmax) ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)];
-  } else if (tid >= 256 && tid < 260) {
-    shn[tid - 256] = nprim[q * 4 + (tid - 256)];
-  }
-  build_htab(s.ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, SLAB, tid);
-  build_htab(s.qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, SLAB, tid);
-  uint2 rent[SLAB ? kRPerThread : kRPerBox];
-  load_rtab(rent, rtab_L, cp.L, tid);
-  __syncthreads();
-
-  const int Ka = shn[0], Kb = shn[1], Kc = shn[2], Kd = shn[3];
-  const int row0 = rt * RB * 16;
-  if (Ka < 1 || Ka > kmax || Kb < 1 || Kb > kmax || Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax) {
-    const int nrows = min(RB * 16, cp.nab - row0);
-    double* o = outq + (int64_t)row0 * cp.ncd;
-    for (int i = tid; i < nrows * cp.ncd; i += kThreads) o[i] = __builtin_nan("");
-    __syncthreads();
-    return;
-  }
-  const int nc1 = (wave < cp.nqb) ? min(kMaxC1, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
-  const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                             // valid row blocks of this tile
-#define BODY(NR, NC1) fused_body<NR, NC1, SLAB, F32>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane)
-  constexpr int NR2 = RB >= 2 ? 2 : 1;
-  if (nrv == NR2 && NR2 == 2) {
-    switch (nc1) {
-      case 0: BODY(NR2, 0); break;
-      case 1: BODY(NR2, 1); break;
-      case 2: BODY(NR2, 2); break;
-      case 3: BODY(NR2, 3); break;
-      default: BODY(NR2, 4); break;
-    }
-  } else if constexpr (SLAB) {
-    switch (nc1) {
-      case 0: BODY(1, 0); break;
-      case 1: BODY(1, 1); break;
-      case 2: BODY(1, 2); break;
-      case 3: BODY(1, 3); break;
-      case 4: BODY(1, 4); break;
-      case 5: BODY(1, 5); break;
-      default: BODY(1, 6); break;
-    }
-  } else {
-    switch (nc1) {
-      case 0: BODY(1, 0); break;
-      case 1: BODY(1, 1); break;
-      case 2: BODY(1, 2); break;
-      case 3: BODY(1, 3); break;
-      default: BODY(1, 4); break;
-    }
-  }
-#undef BODY
-}
-
-// One workgroup = one quartet x one tile of RB*16 bra rows; 8 waves.  Grid:
-// quartets q0.. in order, cp.nrt tiles each.
-template <int RB, bool SLAB>
-__global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
-    const ClassParams cp, const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
-    const double* __restrict__ centers, const double* __restrict__ exps,
-    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, double* __restrict__ out,
-    int64_t q0) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
-  const int64_t q = q0 + blockIdx.x / cp.nrt;
-  const int rt = blockIdx.x % cp.nrt;
-  process_tile<RB, SLAB, false>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
-                         out + q * (int64_t)cp.nab * cp.ncd, q, rt, tid, wave, lane);
-}
-
-// Persistent kernel for a plan: work items {quartet, row tile | class << 16},
-// largest first, taken from a device counter until none are left (every
-// workgroup exits once the counter passes nitems).  qoff[q] is where quartet
-// q's integrals start in out.  Each class brings its own tile height and R
-// layout.  F32: both transforms on FP32 matrix cores (eri4_plan_create).
-template <bool F32>
-__global__ __launch_bounds__(kThreads, 1) void eri4_plan_kernel(
-    const ClassParams* __restrict__ classes, const int2* __restrict__ items, int nitems,
-    const int64_t* __restrict__ qoff, const int32_t* __restrict__ nprim, int* __restrict__ counter,
-    const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
-    const double* __restrict__ centers, const double* __restrict__ exps,
-    const double* __restrict__ coefs, double* __restrict__ out) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  __shared__ int next_item;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  for (;;) {
-    if (tid == 0) next_item = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(next_item);
-    __syncthreads();
-    if (it >= nitems) break;
-    const int2 w = items[it];
-    const int q = __builtin_amdgcn_readfirstlane(w.x);
-    const int rc = __builtin_amdgcn_readfirstlane(w.y);
-    const ClassParams cp = classes[rc >> 16];
-    const int rt = rc & 0xffff;
-    const uint2* rt_L = rtab + cp.rtab_off;
-    double* oq = out + qoff[q];
-    if (cp.slab) {
-      if (cp.rb == 2)
-        process_tile<2, true, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
-      else
-        process_tile<1, true, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
-    } else {
-      if (cp.rb == 2)
-        process_tile<2, false, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
-      else
-        process_tile<1, false, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
-    }
-  }
-}
 
 __global__ void reset_counter_kernel(int* counter) {
   if (threadIdx.x == 0) counter[0] = 0;
@@ -785,23 +142,10 @@ std::vector<DeviceState> g_dev;
     if (e_ != hipSuccess) return fail(ERI4_ERROR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-template <int RB, bool SLAB>
-eri4_status set_attr_one() {
-  HIP_TRY(hipFuncSetAttribute((const void*)eri4_fused_kernel<RB, SLAB>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes));
-  return ERI4_SUCCESS;
-}
-
 eri4_status set_attrs() {
-  eri4_status s;
-  if ((s = set_attr_one<1, false>()) != ERI4_SUCCESS) return s;
-  if ((s = set_attr_one<2, false>()) != ERI4_SUCCESS) return s;
-  if ((s = set_attr_one<1, true>()) != ERI4_SUCCESS) return s;
-  if ((s = set_attr_one<2, true>()) != ERI4_SUCCESS) return s;
-  HIP_TRY(hipFuncSetAttribute((const void*)eri4_plan_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kMaxLdsBytes - 64));
-  HIP_TRY(hipFuncSetAttribute((const void*)eri4_plan_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kMaxLdsBytes - 64));
+  HIP_TRY(fused_set_attrs());
+  HIP_TRY(plan_set_attrs_f64());
+  HIP_TRY(plan_set_attrs_f32());
   HIP_TRY(hipFuncSetAttribute((const void*)hermite_r_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLdsBytes));
   return ERI4_SUCCESS;
@@ -840,7 +184,7 @@ eri4_status ensure_device(DeviceState** st) {
 int align16(int x) { return (x + 15) & ~15; }
 
 // Class parameters and LDS layout for a tile of rb*16 bra rows.
-ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool slab) {
+ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool slab, bool box2) {
   ClassParams p{};
   p.rb = rb;
   p.slab = slab ? 1 : 0;
@@ -866,7 +210,10 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool s
   p.o_qtab = off;  off = align16(off + 16 * p.nqb * 8);
   p.o_union = off;
   const int box_b = r_cells(slab, p.L) * 8;
-  const int ph1 = align16(box_b) + 3 * p.tbaxis * 8;
+  p.lay = slab ? kLaySlab : (box2 ? kLayBox2 : kLayBox);
+  // phase 1: R box, bra tables[, second R box]
+  p.o_box1 = off + align16(box_b) + align16(3 * p.tbaxis * 8);
+  const int ph1 = box2 ? p.o_box1 - off + box_b : align16(box_b) + 3 * p.tbaxis * 8;
   const int xb = align16(rb * 16 * p.xs * 8);
   const int ph2 = xb + 3 * p.tkaxis * 8;
   p.o_brae = off + align16(box_b);
@@ -877,28 +224,26 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool s
 }
 
 // Class parameters: the first of (32-row tiles, box), (16, box), (32, slab),
-// (16, slab) that fits in LDS (limit: bytes available for the dynamic area).
+// (16, slab) that fits in LDS (limit: bytes available for the dynamic area),
+// first with room for a second box (kLayBox2, total order <= kBox2LMax), then
+// without.
 bool pick_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, int limit, ClassParams* out) {
   const int rbs[4] = {2, 1, 2, 1};
   const bool slabs[4] = {false, false, true, true};
-  for (int i = 0; i < 4; ++i) {
-    ClassParams p = make_params(la, lb, lc, ld, kmax, rbs[i], slabs[i]);
-    if (p.lds_bytes > limit || p.L > kMaxL || (p.nqb + 7) / 8 > (slabs[i] && rbs[i] == 1 ? kMaxC1 : 4)) continue;
-    if (!slabs[i] && p.L > kBoxLMax) continue;  // the box recursion holds kRPerBox entries per thread
-    p.rtab_off = d->rstart[(slabs[i] ? 1 : 0) * (kMaxL + 1) + p.L];
-    *out = p;
-    return true;
+  for (int two = 1; two >= 0; --two) {
+    if (two && la + lb + lc + ld > kBox2LMax) continue;
+    for (int i = 0; i < 4; ++i) {
+      if (two && slabs[i]) continue;
+      ClassParams p = make_params(la, lb, lc, ld, kmax, rbs[i], slabs[i], two != 0);
+      const int maxc = slabs[i] && rbs[i] == 1 ? kMaxC1 : 4;
+      if (p.lds_bytes > limit || p.L > kMaxL || (p.nqb + 7) / 8 > maxc) continue;
+      if (!slabs[i] && p.L > kBoxLMax) continue;  // the box recursion holds kRPerBox entries per thread
+      p.rtab_off = d->rstart[(slabs[i] ? 1 : 0) * (kMaxL + 1) + p.L];
+      *out = p;
+      return true;
+    }
   }
   return false;
-}
-
-template <int RB, bool SLAB>
-hipError_t launch_fused(const ClassParams& p, dim3 grid, hipStream_t s, const DeviceState* d,
-                        const double* c, const double* e, const double* co, const int32_t* np, double* out,
-                        int64_t q0) {
-  hipLaunchKernelGGL((eri4_fused_kernel<RB, SLAB>), grid, dim3(kThreads), p.lds_bytes, s, p, d->boys, d->rtab, c,
-                     e, co, np, out, q0);
-  return hipGetLastError();
 }
 
 }  // namespace
@@ -951,13 +296,8 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets, const 
   for (int64_t q0 = 0; q0 < nquartets; q0 += qchunk) {
     const int64_t nq = (nquartets - q0 < qchunk) ? nquartets - q0 : qchunk;
     const dim3 grid((unsigned)(nq * p.nrt));
-    hipError_t e;
-    if (p.slab)
-      e = (p.rb == 2) ? launch_fused<2, true>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0)
-                      : launch_fused<1, true>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0);
-    else
-      e = (p.rb == 2) ? launch_fused<2, false>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0)
-                      : launch_fused<1, false>(p, grid, stream, d, centers, exponents, coeffs, nprim, out, q0);
+    const hipError_t e =
+        fused_launch(p, grid, stream, Tables{d->boys, d->rtab}, centers, exponents, coeffs, nprim, out, q0);
     if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
   }
   return ERI4_SUCCESS;
@@ -1086,9 +426,7 @@ eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* 
   int ncu = 0, per_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
   const hipError_t oe =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, p->f32 ? (const void*)eri4_plan_kernel<true> : (const void*)eri4_plan_kernel<false>, kThreads,
-          p->lds_bytes);
+      p->f32 ? plan_occupancy_f32(p->lds_bytes, &per_cu) : plan_occupancy_f64(p->lds_bytes, &per_cu);
   if (oe != hipSuccess || per_cu < 1) per_cu = 1;
   p->grid = (int)std::min<int64_t>(std::max(p->nitems, 1), (int64_t)ncu * per_cu);
 
@@ -1142,15 +480,11 @@ eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const doubl
   if (st != ERI4_SUCCESS) return st;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, plan->d_counter);
   HIP_TRY(hipGetLastError());
-  if (plan->f32)
-    hipLaunchKernelGGL(eri4_plan_kernel<true>, dim3(plan->grid), dim3(kThreads), plan->lds_bytes, stream,
-                       plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter,
-                       d->boys, d->rtab, centers, exponents, coeffs, out);
-  else
-    hipLaunchKernelGGL(eri4_plan_kernel<false>, dim3(plan->grid), dim3(kThreads), plan->lds_bytes, stream,
-                       plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter,
-                       d->boys, d->rtab, centers, exponents, coeffs, out);
-  HIP_TRY(hipGetLastError());
+  const PlanArgs a{plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter,
+                   centers, exponents, coeffs, out};
+  const Tables t{d->boys, d->rtab};
+  HIP_TRY(plan->f32 ? plan_launch_f32(dim3(plan->grid), plan->lds_bytes, stream, t, a)
+                    : plan_launch_f64(dim3(plan->grid), plan->lds_bytes, stream, t, a));
   return ERI4_SUCCESS;
 }
 

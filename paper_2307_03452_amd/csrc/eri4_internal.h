@@ -62,6 +62,9 @@ __host__ __device__ constexpr int r_offset(bool slab, int L, int t, int u, int v
 // t, u, v).  The first entry of each table is (0,0,0) with all fields 0.
 constexpr int kRtabEntries = 35960;  // sum_{L=0}^{28} nherm(L), per layout
 
+// LDS of one compute unit (gfx950).
+constexpr int kMaxLdsBytes = 160 * 1024;
+
 // One workgroup computes a tile of 16 or 32 bra rows (ab) of one quartet.
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * 64;
@@ -69,6 +72,14 @@ constexpr int kRPerThread = (nherm(kMaxL) + kThreads - 1) / kThreads;  // 9, sla
 constexpr int kBoxLMax = 24;                                              // box layout only up to here
 constexpr int kRPerBox = (nherm(kBoxLMax) + kThreads - 1) / kThreads;     // 6
 constexpr int kMaxC1 = 6;  // first-transform column blocks per wave (L_ket <= 14)
+// Layouts of the R recursion (template parameter of the kernels):
+//   kLayBox   box, eq. (md1) in place (two barriers per level)
+//   kLaySlab  slab, in place
+//   kLayBox2  two boxes, levels alternate between them (one barrier per
+//             level); [r]^(0) ends in the first.  Fits in LDS up to total
+//             order kBox2LMax.
+constexpr int kLayBox = 0, kLaySlab = 1, kLayBox2 = 2;
+constexpr int kBox2LMax = 19;
 
 // Everything the fused kernel needs to know about one class (la lb|lc ld).
 struct ClassParams {
@@ -89,6 +100,8 @@ struct ClassParams {
   int rtab_off;        // first entry (uint2 units) of the recursion table for this layout and L
   int slab;            // R layout: 0 box, 1 slab
   int rb;              // 16-row blocks per tile (1 or 2)
+  int lay;             // kLayBox, kLaySlab or kLayBox2 (slab == (lay == kLaySlab))
+  int o_box1;          // kLayBox2: byte offset of the second R box
   // LDS layout (byte offsets)
   int o_union;   // phase 1: R box then bra tables; phase 2: [ab|q] tile then ket tables
   int o_brae;    // bra tables (phase 1)
