@@ -15,6 +15,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -114,18 +116,25 @@ def time_plan(b, precision, steps, warmup):
     return plan, out, (time.perf_counter() - t0) / steps
 
 
-def sampled_oracle_err(b, plan, out, absolute=False):
-    """Largest error against the oracle over a few quartets of batch b (the one
-    with the largest total l and three random ones, among quartets whose four
-    contraction lengths multiply to at most 16, which the oracle does quickly):
-    relative to each quartet's largest integral, or absolute."""
-    import numpy as np
+def sampled_oracle_err(b, plan, out, absolute=False, smallest=False):
+    """Largest error against the oracle over a few quartets of batch b,
+    relative to each quartet's largest integral, or absolute.  The sample: the
+    quartet with the largest total l and three random ones among quartets whose
+    four contraction lengths multiply to at most 16 (which the oracle does
+    quickly); with smallest=True, the two with the smallest total l and one
+    random one among those with total l <= 17."""
     import oracle
     from paper_2307_03452_amd import inputs
     off = plan.offsets()
-    cheap = np.flatnonzero(np.prod(b.nprim, axis=1) <= 16)
-    big = cheap[np.argmax(b.lq[cheap].sum(axis=1))]
-    idx = sorted({int(big), *np.random.default_rng(7).choice(cheap, 3, replace=False).tolist()})
+    rng = np.random.default_rng(7)
+    if smallest:
+        tot = b.lq.sum(axis=1)
+        small = np.flatnonzero(tot <= 17)
+        idx = sorted({*np.argsort(tot, kind="stable")[:2].tolist(), int(rng.choice(small))})
+    else:
+        cheap = np.flatnonzero(np.prod(b.nprim, axis=1) <= 16)
+        big = cheap[np.argmax(b.lq[cheap].sum(axis=1))]
+        idx = sorted({int(big), *rng.choice(cheap, 3, replace=False).tolist()})
     err = 0.0
     for q in idx:
         s_ = inputs.subset(b, [q])
@@ -164,6 +173,97 @@ def time_uneven(steps, warmup, nq=20000, seed=1004, mixed_steps=0):
         mixed.update(class_errors(b, plan, out, out32))
         del out32
     return rec, mixed
+
+
+def time_classes_l7(reps=1):
+    """(kk|kk) and (ik|ik), K=3 per shell, 256 quartets each: eri4_batch (FP64)
+    and a one-class plan with FP32 transforms."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs, metrics
+    d = lambda a: torch.from_numpy(a).cuda()
+    out = []
+    for ls, seed in (((7, 7, 7, 7), 1005), ((6, 7, 6, 7), 1007)):
+        b = inputs.class_batch(ls, 256, 3, seed=seed, exp_range=(0.05, 200.0))
+        C, E, Co, N = d(b.centers), d(b.exps), d(b.coefs), d(b.nprim)
+        o = eri4.batch(ls, C, E, Co, N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eri4.batch(ls, C, E, Co, N, out=o)
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - t0) / reps
+        b.lq = np.tile(np.array(ls, np.int32), (b.nq, 1))
+        _, o32, t32 = time_plan(b, "fp32", reps, 1)
+        err = float((o32 - o.reshape(-1)).abs().max())
+        flops = b.nq * metrics.md4_flops(*ls, 9, 9)
+        ints = b.nq * metrics.integrals_per_quartet(*ls)
+        out.append({"class": "(%d%d|%d%d)" % ls, "quartets": b.nq, "K_per_shell": 3,
+                    "value": ints / t64, "unit": "integrals/s", "ms_per_step": t64 * 1e3,
+                    "pct_fp64_peak": 100 * flops / t64 / 1e12 / FP64_PEAK_TFLOPS,
+                    "fp32_speedup_vs_fp64": t64 / t32, "fp32_max_abs_err_vs_fp64": err})
+        del o, o32
+    return out
+
+
+def time_stream(nq=50000, seed=1006, chunk=1024, ring=4):
+    """Serving-style stream: 50 000 quartets over the 256 classes in {4..7}^4
+    (Zipf counts, K=3 per shell) in chunks of 1024, each chunk a HIP graph
+    (the plan's counter reset and persistent kernel) replayed into a ring of
+    output buffers; FP64 and FP32 transforms."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs
+    b = inputs.stream_batch(nq, seed)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    C, E, Co = d(b.centers), d(b.exps), d(b.coefs)
+    starts = list(range(0, nq, chunk))
+    views = [(C[s0:s0 + chunk], E[s0:s0 + chunk], Co[s0:s0 + chunk]) for s0 in starts]
+    flops = md4_flops_batch(b.lq, b.nprim)
+    rec = {"workload": f"stream of {nq} quartets, 256 classes (la lb|lc ld) in {{4,5,6,7}}^4 with Zipf(1.2) counts, "
+                       f"K=3 per shell, exponents [0.05,200]; chunks of {chunk} quartets, each a HIP graph replayed "
+                       f"into a ring of {ring} output buffers", "chunks": len(starts)}
+    check = {}
+    for prec in ("fp64", "fp32"):
+        plans = [eri4.Plan(b.lq[s0:s0 + chunk], b.nprim[s0:s0 + chunk], b.kmax, precision=prec) for s0 in starts]
+        size = max(p.output_size for p in plans)
+        outs = [torch.empty(size, dtype=torch.float64, device="cuda") for _ in range(ring)]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        plans[0].execute(*views[0], out=outs[0], stream=side)  # first use of the device outside capture
+        torch.cuda.synchronize()
+        graphs = []
+        for i, p in enumerate(plans):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                p.execute(*views[i], out=outs[i % ring], stream=side)
+            graphs.append(g)
+        for g in graphs[:2]:
+            g.replay()
+        torch.cuda.synchronize()
+        cur = torch.cuda.current_stream()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in graphs]
+        t0 = time.perf_counter()
+        for (a, z), g in zip(evs, graphs):
+            a.record(cur)
+            g.replay()
+            z.record(cur)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([a.elapsed_time(z) for a, z in evs])
+        ints = sum(p.output_size for p in plans)
+        rec[prec] = {"value": ints / wall, "unit": "integrals/s", "s_per_pass": wall,
+                     "pct_fp64_peak": 100 * flops / wall / 1e12 / FP64_PEAK_TFLOPS,
+                     "chunk_ms_p50": float(np.percentile(lat, 50)), "chunk_ms_p99": float(np.percentile(lat, 99))}
+        # the first chunk, kept for the FP32-vs-FP64 comparison
+        graphs[0].replay()
+        torch.cuda.synchronize()
+        check[prec] = (plans[0], outs[0][:plans[0].output_size].clone())
+        if prec == "fp64":
+            rec["fp64"]["oracle_max_rel_err_sampled"] = sampled_oracle_err(inputs.subset(b, range(chunk)), plans[0],
+                                                                           check["fp64"][1], smallest=True)
+        del graphs, outs
+    rec["fp32_speedup_vs_fp64"] = rec["fp64"]["s_per_pass"] / rec["fp32"]["s_per_pass"]
+    rec["fp32_max_abs_err_vs_fp64_first_chunk"] = float((check["fp32"][1] - check["fp64"][1]).abs().max())
+    return rec
 
 
 def class_errors(b, plan, ref, test, target=1e-10):
@@ -243,6 +343,8 @@ def main():
                     help="timed steps of the 20k-quartet mixed-class batch reported beside the headline (0: skip)")
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="timed steps of the mixed-batch with FP32 transforms, compared with FP64 (0: skip)")
+    ap.add_argument("--stream-steps", type=int, default=1,
+                    help="run the l=7 classes and the 50k-quartet serving stream (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -297,6 +399,9 @@ def main():
         rec["uneven"], mixed = time_uneven(args.uneven_steps, 1, mixed_steps=args.mixed_steps)
         if mixed is not None:
             rec["mixed_precision"] = mixed
+    if args.stream_steps > 0 and args.workload == "iiii_k1":
+        rec["l7_classes"] = time_classes_l7()
+        rec["stream"] = time_stream()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

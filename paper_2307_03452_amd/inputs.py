@@ -147,6 +147,12 @@ def iiii(K: int = 1, nq: int = 512, seed: int | None = None) -> Batch:
     return class_batch((6, 6, 6, 6), nq, K, seed, exp_range=(0.05, 200.0))
 
 
+def stream_batch(nq: int = 50000, seed: int = 1006) -> Batch:
+    """Serving-style stream: 50 000 quartets over the 256 ordered classes in
+    {4,5,6,7}^4 with Zipf(1.2) class counts, 3 primitives per shell."""
+    return uneven_batch(nq=nq, seed=seed, lvals=(4, 5, 6, 7), k_fixed=3)
+
+
 def zipf_classes(lvals=(4, 5, 6), s=1.2):
     """Ordered classes (la lb|lc ld) over lvals^4, ranked by (total L, tuple),
     with probabilities proportional to rank^-s."""
@@ -157,15 +163,20 @@ def zipf_classes(lvals=(4, 5, 6), s=1.2):
 
 
 def uneven_batch(nq: int = 20000, seed: int = 1004, lvals=(4, 5, 6), kmax: int = 8,
-                 exp_range=(0.05, 200.0), box: float = 8.0) -> Batch:
+                 exp_range=(0.05, 200.0), box: float = 8.0, k_fixed: int | None = None) -> Batch:
     """Mixed batch: class counts multinomial over Zipf(1.2) ranked classes,
-    quartets shuffled, contraction length per shell uniform in 1..kmax."""
+    quartets shuffled, contraction length per shell uniform in 1..kmax (or
+    k_fixed for every shell, with kmax = k_fixed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     cls, p = zipf_classes(lvals)
     counts = rng.multinomial(nq, p)
     lq = np.repeat(np.array(cls, dtype=np.int32), counts, axis=0)
     lq = lq[rng.permutation(nq)]
-    nprim = rng.integers(1, kmax + 1, size=(nq, 4)).astype(np.int32)
+    if k_fixed is not None:
+        kmax = int(k_fixed)
+        nprim = np.full((nq, 4), kmax, dtype=np.int32)
+    else:
+        nprim = rng.integers(1, kmax + 1, size=(nq, 4)).astype(np.int32)
     centers = rng.uniform(0.0, box, size=(nq, 4, 3))
     lo, hi = exp_range
     exps = np.exp(rng.uniform(np.log(lo), np.log(hi), size=(nq, 4, kmax)))
