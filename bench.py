@@ -98,11 +98,22 @@ def md4_flops_batch(lq, nprim):
     return tot
 
 
-def time_plan(b, precision, steps, warmup):
+TUNE_FILE = os.path.join(ROOT, "paper_2307_03452_amd", "tune_mi355x.json")
+
+
+def tuned_tiles():
+    """The autotuner's table (paper_2307_03452_amd/autotune.py), if present."""
+    if not os.path.exists(TUNE_FILE):
+        return None
+    with open(TUNE_FILE) as f:
+        return json.load(f)["entries"]
+
+
+def time_plan(b, precision, steps, warmup, tiles=None):
     """One plan over batch b (inputs resident in HBM): wall seconds per execute."""
     import torch
     from paper_2307_03452_amd import eri4
-    plan = eri4.Plan(b.lq, b.nprim, b.kmax, precision=precision)
+    plan = eri4.Plan(b.lq, b.nprim, b.kmax, precision=precision, tiles=tiles)
     d = lambda a: torch.from_numpy(a).cuda()
     C, E, Co = d(b.centers), d(b.exps), d(b.coefs)
     out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
@@ -155,15 +166,17 @@ def time_uneven(steps, warmup, nq=20000, seed=1004, mixed_steps=0):
     mixed_steps > 0 the same batch also runs with FP32 transforms."""
     from paper_2307_03452_amd import inputs
     b = inputs.uneven_batch(nq=nq, seed=seed)
-    plan, out, wall = time_plan(b, "fp64", steps, warmup)
+    tiles = tuned_tiles()
+    plan, out, wall = time_plan(b, "fp64", steps, warmup, tiles)
     flops = md4_flops_batch(b.lq, b.nprim)
     rec = {"workload": UNEVEN_DESC.format(nq=nq),
            "value": plan.output_size / wall, "unit": "integrals/s", "ms_per_step": wall * 1e3,
            "md4_tflops": flops / wall / 1e12, "pct_fp64_peak": 100 * flops / wall / 1e12 / FP64_PEAK_TFLOPS,
-           "parity_max_rel_err_sampled": sampled_oracle_err(b, plan, out), "quartets": nq}
+           "parity_max_rel_err_sampled": sampled_oracle_err(b, plan, out), "quartets": nq,
+           "tiles": "autotuned table (tune_mi355x.json)" if tiles else "library default"}
     mixed = None
     if mixed_steps > 0:
-        plan32, out32, wall32 = time_plan(b, "fp32", mixed_steps, 1)
+        plan32, out32, wall32 = time_plan(b, "fp32", mixed_steps, 1, tiles)
         mixed = {"workload": UNEVEN_DESC.format(nq=nq), "precision": "fp32",
                  "transforms": "operands rounded to FP32, FP32 matrix cores, FP32 accumulation; "
                                "Boys, R and E in FP64",

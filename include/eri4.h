@@ -156,6 +156,35 @@ typedef struct eri4_plan_s* eri4_plan;
 
 eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
                              int kmax, eri4_precision precision);
+
+/*
+ * Tile choices for plans (what an autotuner picks per class and contraction
+ * size).  A tile is 16 * rows16 bra rows of one quartet; the Hermite integrals
+ * of eq. (md1) live in LDS in one of three layouts:
+ *   ERI4_LAYOUT_BOX   (L+1)^3 box, recursion in place            (L <= 24)
+ *   ERI4_LAYOUT_SLAB  t-slabs, about half the space, in place      (L <= 28)
+ *   ERI4_LAYOUT_BOX2  two boxes, levels alternate between them     (L <= 19)
+ * where L = la+lb+lc+ld.  A choice applies to the quartets of class l whose
+ * product of the four contraction lengths lies in [kq_min, kq_max].
+ */
+typedef enum { ERI4_LAYOUT_BOX = 0, ERI4_LAYOUT_SLAB = 1, ERI4_LAYOUT_BOX2 = 2 } eri4_layout;
+
+typedef struct {
+  int32_t l[4];           /* class (la lb|lc ld) */
+  int32_t kq_min, kq_max; /* range of nprim[a]*nprim[b]*nprim[c]*nprim[d] */
+  int32_t rows16;         /* 1 or 2 */
+  int32_t layout;         /* eri4_layout */
+} eri4_tile_choice;
+
+/* eri4_plan_create with tile choices (HOST array of nchoices entries, may be
+ * NULL when nchoices == 0).  For each quartet the first matching entry is
+ * used; quartets no entry matches get the library's own choice.  A matching
+ * entry whose tile does not fit (LDS, or L beyond the layout's limit) or has
+ * rows16/layout out of range gives INVALID_ARGUMENT naming it.  Otherwise as
+ * eri4_plan_create, which is this call with no choices. */
+eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
+                                   int kmax, eri4_precision precision, const eri4_tile_choice* choices,
+                                   int nchoices);
 int64_t eri4_plan_output_size(eri4_plan plan);                         /* doubles; -1 if plan is NULL */
 eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets); /* HOST int64 [nquartets] */
 eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents,

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -223,26 +224,30 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool s
   return p;
 }
 
-// Class parameters: the first of (32-row tiles, box), (16, box), (32, slab),
-// (16, slab) that fits in LDS (limit: bytes available for the dynamic area),
-// first with room for a second box (kLayBox2, total order <= kBox2LMax), then
-// without.
+// Class parameters for one tile height and R layout, if they fit (limit:
+// bytes of LDS available for the dynamic area; column blocks per wave within
+// what the kernel bodies are instantiated for).
+bool try_params(int la, int lb, int lc, int ld, int kmax, int rb, int lay, const DeviceState* d, int limit,
+                ClassParams* out) {
+  const bool slab = lay == kLaySlab, two = lay == kLayBox2;
+  if ((rb != 1 && rb != 2) || lay < kLayBox || lay > kLayBox2) return false;
+  if (two && la + lb + lc + ld > kBox2LMax) return false;
+  ClassParams p = make_params(la, lb, lc, ld, kmax, rb, slab, two);
+  const int maxc = slab && rb == 1 ? kMaxC1 : 4;
+  if (p.lds_bytes > limit || p.L > kMaxL || (p.nqb + 7) / 8 > maxc) return false;
+  if (!slab && p.L > kBoxLMax) return false;  // the box recursion holds kRPerBox entries per thread
+  p.rtab_off = d->rstart[(slab ? 1 : 0) * (kMaxL + 1) + p.L];
+  *out = p;
+  return true;
+}
+
+// The library's own choice: the first that fits of two boxes (32-row tiles,
+// then 16), box, slab.
 bool pick_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, int limit, ClassParams* out) {
-  const int rbs[4] = {2, 1, 2, 1};
-  const bool slabs[4] = {false, false, true, true};
-  for (int two = 1; two >= 0; --two) {
-    if (two && la + lb + lc + ld > kBox2LMax) continue;
-    for (int i = 0; i < 4; ++i) {
-      if (two && slabs[i]) continue;
-      ClassParams p = make_params(la, lb, lc, ld, kmax, rbs[i], slabs[i], two != 0);
-      const int maxc = slabs[i] && rbs[i] == 1 ? kMaxC1 : 4;
-      if (p.lds_bytes > limit || p.L > kMaxL || (p.nqb + 7) / 8 > maxc) continue;
-      if (!slabs[i] && p.L > kBoxLMax) continue;  // the box recursion holds kRPerBox entries per thread
-      p.rtab_off = d->rstart[(slabs[i] ? 1 : 0) * (kMaxL + 1) + p.L];
-      *out = p;
-      return true;
-    }
-  }
+  static const int order[6][2] = {{2, kLayBox2}, {1, kLayBox2}, {2, kLayBox},
+                                  {1, kLayBox},  {2, kLaySlab}, {1, kLaySlab}};
+  for (const auto& o : order)
+    if (try_params(la, lb, lc, ld, kmax, o[0], o[1], d, limit, out)) return true;
   return false;
 }
 
@@ -338,6 +343,15 @@ static void plan_free(eri4_plan_s* p) {
 
 eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim, int kmax,
                              eri4_precision precision) {
+  return eri4_plan_create_tuned(plan, nquartets, l, nprim, kmax, precision, nullptr, 0);
+}
+
+static_assert(ERI4_LAYOUT_BOX == kLayBox && ERI4_LAYOUT_SLAB == kLaySlab && ERI4_LAYOUT_BOX2 == kLayBox2,
+              "public and internal layout codes agree");
+
+eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
+                                   int kmax, eri4_precision precision, const eri4_tile_choice* choices,
+                                   int nchoices) {
   g_err.clear();
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
   *plan = nullptr;
@@ -357,35 +371,75 @@ eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* 
       return fail(ERI4_ERROR_INVALID_ARGUMENT, "contraction length %d outside 1..%d at quartet %lld", nprim[i], kmax,
                   (long long)(i / 4));
   }
+  if (nchoices < 0 || (nchoices > 0 && !choices))
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choices: NULL array or negative count");
+  // entries of the choice table per class, in table order
+  std::vector<std::vector<int>> choices_of(8 * 8 * 8 * 8);
+  for (int i = 0; i < nchoices; ++i) {
+    const eri4_tile_choice& c = choices[i];
+    if (c.rows16 != 1 && c.rows16 != 2)
+      return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d: rows16 must be 1 or 2 (got %d)", i, c.rows16);
+    if (c.layout < ERI4_LAYOUT_BOX || c.layout > ERI4_LAYOUT_BOX2)
+      return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d: unknown layout %d", i, c.layout);
+    if (c.kq_min > c.kq_max)
+      return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d: kq_min %d above kq_max %d", i, c.kq_min, c.kq_max);
+    for (int x = 0; x < 4; ++x)
+      if (c.l[x] < 0 || c.l[x] > ERI4_MAX_L)
+        return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d: angular momentum %d out of range", i, c.l[x]);
+    choices_of[((c.l[0] * 8 + c.l[1]) * 8 + c.l[2]) * 8 + c.l[3]].push_back(i);
+  }
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
   DeviceState* d;
   eri4_status st = ensure_device(&d);
   if (st != ERI4_SUCCESS) return st;
   eri4_plan_s* p = new (std::nothrow) eri4_plan_s();
   if (!p) return fail(ERI4_ERROR_OUT_OF_MEMORY, "host allocation failed");
-  HIP_TRY(hipGetDevice(&p->device));
+  p->device = device;
   p->nq = nquartets;
   p->kmax = kmax;
   p->f32 = precision == ERI4_PREC_FP32;
 
-  // classes present, keyed by (la,lb,lc,ld)
-  std::vector<int> cls_of_key(8 * 8 * 8 * 8, -1);
+  // groups of quartets with the same class and tile choice (the first matching
+  // entry of the table, or none), keyed by class * (nchoices + 1) + entry + 1
+  std::map<int64_t, int> group_of;
   std::vector<int> qcls(nquartets);
-  std::vector<std::array<int, 4>> keys;
+  std::vector<std::array<int, 5>> keys;  // la, lb, lc, ld, entry (-1: none)
   for (int64_t q = 0; q < nquartets; ++q) {
     const int key = ((l[4 * q] * 8 + l[4 * q + 1]) * 8 + l[4 * q + 2]) * 8 + l[4 * q + 3];
-    if (cls_of_key[key] < 0) {
-      cls_of_key[key] = (int)keys.size();
-      keys.push_back({l[4 * q], l[4 * q + 1], l[4 * q + 2], l[4 * q + 3]});
+    const int64_t kq = (int64_t)nprim[4 * q] * nprim[4 * q + 1] * nprim[4 * q + 2] * nprim[4 * q + 3];
+    int entry = -1;
+    for (int i : choices_of[key])
+      if (kq >= choices[i].kq_min && kq <= choices[i].kq_max) {
+        entry = i;
+        break;
+      }
+    const int64_t gkey = (int64_t)key * (nchoices + 1) + entry + 1;
+    auto it = group_of.find(gkey);
+    if (it == group_of.end()) {
+      it = group_of.emplace(gkey, (int)keys.size()).first;
+      keys.push_back({l[4 * q], l[4 * q + 1], l[4 * q + 2], l[4 * q + 3], entry});
     }
-    qcls[q] = cls_of_key[key];
+    qcls[q] = it->second;
   }
-  // per class: tile height and R layout (see pick_params)
+  if (keys.size() > 32767) {
+    plan_free(p);
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "too many (class, tile choice) groups");
+  }
+  // per group: tile height and R layout (the table's, or see pick_params)
   std::vector<ClassParams> cps(keys.size());
   for (size_t c = 0; c < keys.size(); ++c) {
-    if (!pick_params(keys[c][0], keys[c][1], keys[c][2], keys[c][3], kmax, d, kMaxLdsBytes - 64, &cps[c])) {
+    const auto& k = keys[c];
+    if (k[4] >= 0) {
+      const eri4_tile_choice& ch = choices[k[4]];
+      if (!try_params(k[0], k[1], k[2], k[3], kmax, ch.rows16, ch.layout, d, kMaxLdsBytes - 64, &cps[c])) {
+        plan_free(p);
+        return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d (rows16 %d, layout %d) does not fit class (%d %d|%d %d)",
+                    k[4], ch.rows16, ch.layout, k[0], k[1], k[2], k[3]);
+      }
+    } else if (!pick_params(k[0], k[1], k[2], k[3], kmax, d, kMaxLdsBytes - 64, &cps[c])) {
       plan_free(p);
-      return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", keys[c][0], keys[c][1],
-                  keys[c][2], keys[c][3]);
+      return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", k[0], k[1], k[2], k[3]);
     }
   }
   p->nclasses = (int)keys.size();

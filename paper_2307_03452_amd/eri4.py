@@ -19,13 +19,34 @@ ERI4_MAX_BOYS_M = 28
 
 # eri4_precision: arithmetic of the two transforms of a plan
 PRECISION = {"fp64": 0, "fp32": 1}
+# eri4_layout: where the Hermite integrals of a tile live in LDS
+LAYOUT = {"box": 0, "slab": 1, "box2": 2}
+
+
+class TileChoice(ctypes.Structure):
+    """eri4_tile_choice: tile height and R layout for the quartets of class l
+    whose product of the four contraction lengths is in [kq_min, kq_max]."""
+    _fields_ = [("l", ctypes.c_int32 * 4), ("kq_min", ctypes.c_int32), ("kq_max", ctypes.c_int32),
+                ("rows16", ctypes.c_int32), ("layout", ctypes.c_int32)]
+
+
+def tile_choices(entries):
+    """ctypes array of TileChoice from dicts {"l": (la,lb,lc,ld), "kq": (min, max),
+    "rows16": 1|2, "layout": "box"|"slab"|"box2"}."""
+    arr = (TileChoice * len(entries))()
+    for i, e in enumerate(entries):
+        arr[i].l[:] = [int(x) for x in e["l"]]
+        arr[i].kq_min, arr[i].kq_max = int(e["kq"][0]), int(e["kq"][1])
+        arr[i].rows16 = int(e["rows16"])
+        arr[i].layout = LAYOUT[e["layout"]] if isinstance(e["layout"], str) else int(e["layout"])
+    return arr
 
 STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UNSUPPORTED",
           3: "ERI4_ERROR_OUT_OF_MEMORY", 4: "ERI4_ERROR_HIP", 5: "ERI4_ERROR_INTERNAL"}
 
 # every symbol include/eri4.h declares
 EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version", "eri4_init",
-           "eri4_batch", "eri4_plan_create", "eri4_plan_output_size", "eri4_plan_output_offsets",
+           "eri4_batch", "eri4_plan_create", "eri4_plan_create_tuned", "eri4_plan_output_size", "eri4_plan_output_offsets",
            "eri4_plan_execute", "eri4_plan_destroy", "eri4_boys", "eri4_hermite_r", "eri4_hermite_e")
 
 _lib = None
@@ -57,6 +78,8 @@ def lib() -> ctypes.CDLL:
         L.eri4_batch.restype = c_int
         L.eri4_plan_create.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int]
         L.eri4_plan_create.restype = c_int
+        L.eri4_plan_create_tuned.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int, vp, c_int]
+        L.eri4_plan_create_tuned.restype = c_int
         L.eri4_plan_output_size.argtypes = [vp]
         L.eri4_plan_output_size.restype = i64
         L.eri4_plan_output_offsets.argtypes = [vp, vp]
@@ -170,9 +193,10 @@ class Plan:
 
     lq, nprim: host int32 arrays [nq, 4] (angular momenta, contraction lengths).
     precision: "fp64" or "fp32", the arithmetic of the two transforms.
+    tiles: optional tile choices (see tile_choices), e.g. an autotuner's table.
     """
 
-    def __init__(self, lq, nprim, kmax: int, precision: str = "fp64"):
+    def __init__(self, lq, nprim, kmax: int, precision: str = "fp64", tiles=None):
         import numpy as np
         self._lq = np.ascontiguousarray(lq, dtype=np.int32)
         self._np = np.ascontiguousarray(nprim, dtype=np.int32)
@@ -181,9 +205,12 @@ class Plan:
         self.kmax = int(kmax)
         self.precision = precision
         h = ctypes.c_void_p()
-        _check(lib().eri4_plan_create(ctypes.byref(h), self.nq, self._lq.ctypes.data_as(ctypes.c_void_p),
-                                      self._np.ctypes.data_as(ctypes.c_void_p), self.kmax,
-                                      PRECISION[precision] if isinstance(precision, str) else int(precision)))
+        arr = tile_choices(tiles) if tiles else None
+        _check(lib().eri4_plan_create_tuned(
+            ctypes.byref(h), self.nq, self._lq.ctypes.data_as(ctypes.c_void_p),
+            self._np.ctypes.data_as(ctypes.c_void_p), self.kmax,
+            PRECISION[precision] if isinstance(precision, str) else int(precision),
+            ctypes.cast(arr, ctypes.c_void_p) if arr is not None else None, len(arr) if arr is not None else 0))
         self._h = h
 
     @property

@@ -114,6 +114,29 @@ def test_plan_create_rejects_bad_host_arrays_before_touching_a_device():
     assert L.eri4_plan_destroy(None) == 0
 
 
+def test_plan_create_tuned_rejects_bad_tile_tables_before_touching_a_device():
+    import numpy as np
+    L = eri4.lib()
+    h = ctypes.c_void_p()
+    lq = np.full((3, 4), 4, np.int32)
+    npr = np.ones((3, 4), np.int32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+
+    def create(entries, n=None):
+        arr = eri4.tile_choices(entries)
+        return L.eri4_plan_create_tuned(ctypes.byref(h), 3, ptr(lq), ptr(npr), 1, 0,
+                                        ctypes.cast(arr, ctypes.c_void_p), len(entries) if n is None else n)
+
+    good = {"l": (4, 4, 4, 4), "kq": (1, 1), "rows16": 2, "layout": "box2"}
+    assert create([dict(good, rows16=3)]) == STATUS_INVALID and b"rows16" in L.eri4_last_error()
+    assert create([dict(good, layout=7)]) == STATUS_INVALID and b"layout" in L.eri4_last_error()
+    assert create([dict(good, kq=(5, 2))]) == STATUS_INVALID and b"kq_min" in L.eri4_last_error()
+    assert create([dict(good, l=(4, 4, 8, 4))]) == STATUS_INVALID and b"angular momentum" in L.eri4_last_error()
+    assert create([good], n=-1) == STATUS_INVALID
+    assert L.eri4_plan_create_tuned(ctypes.byref(h), 3, ptr(lq), ptr(npr), 1, 0, None, 2) == STATUS_INVALID
+    assert h.value is None
+
+
 def test_uneven_batch_recipe():
     import numpy as np
     from paper_2307_03452_amd import inputs

@@ -110,6 +110,36 @@ def test_plan_graph_capture_replays(torch):
         torch.cuda.synchronize()
 
 
+def test_tile_choices_give_the_default_results(torch):
+    """Every tile height and R layout that fits gives the integrals of the
+    library's own choice (same arithmetic, other tiling), for classes that
+    can use all three layouts."""
+    b = mixed(24, 25, (4, 5), 3)
+    C, E, Co = dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs)
+    ref = eri4.Plan(b.lq, b.nprim, b.kmax).execute(C, E, Co)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    classes = sorted({tuple(int(x) for x in r) for r in b.lq})
+    for rows16, lay in ((1, "box"), (2, "box"), (1, "box2"), (2, "box2"), (1, "slab"), (2, "slab")):
+        # two boxes fit up to total order 19; other classes keep the default
+        tiles = [{"l": c, "kq": (1, 4096), "rows16": rows16, "layout": lay} for c in classes
+                 if lay != "box2" or sum(c) <= 19]
+        p = eri4.Plan(b.lq, b.nprim, b.kmax, tiles=tiles)
+        g = p.execute(C, E, Co)
+        torch.cuda.synchronize()
+        g = g.cpu().numpy()
+        scale = np.abs(ref).max()
+        assert np.abs(g - ref).max() <= 1e-13 * scale, (rows16, lay, np.abs(g - ref).max() / scale)
+    check(ref, p.offsets(), b, [0, 5, 11])
+
+
+def test_tile_choice_that_does_not_fit_is_rejected(torch):
+    lq = np.array([[6, 6, 6, 6]], np.int32)
+    with pytest.raises(eri4.Eri4Error, match="does not fit"):
+        eri4.Plan(lq, np.ones((1, 4), np.int32), 1, tiles=[{"l": (6, 6, 6, 6), "kq": (1, 1), "rows16": 2,
+                                                            "layout": "box2"}])
+
+
 def test_empty_plan(torch):
     p = eri4.Plan(np.zeros((0, 4), np.int32), np.zeros((0, 4), np.int32), 1)
     assert p.output_size == 0
