@@ -298,3 +298,15 @@ def test_kkkk_contracted_k2(torch):
     g = run_gpu(torch, b)
     o = oracle.eri_md4(b.ls, b.centers, b.exps, b.coefs, b.nprim)
     assert_quartets_close(g, o, label="kkkk K2")
+
+
+def test_maximum_contraction_length(torch):
+    """kmax = ERI4_MAX_K = 16: (ss|ss) with 16 primitives on every shell
+    (65 536 primitive quartets per quartet) and (pd|sp) with mixed lengths."""
+    assert eri4.ERI4_MAX_K == 16
+    for b in (inputs.class_batch((0, 0, 0, 0), 2, 16, seed=31, exp_range=(0.1, 20.0)),
+              inputs.class_batch((1, 2, 0, 1), 3, (1, 16), seed=32, exp_range=(0.1, 20.0), kmax=16)):
+        assert b.kmax == 16
+        g = run_gpu(torch, b)
+        o = oracle.eri_md4(b.ls, b.centers, b.exps, b.coefs, b.nprim)
+        assert_quartets_close(g, o, label=b.ls)

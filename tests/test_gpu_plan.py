@@ -140,6 +140,23 @@ def test_tile_choice_that_does_not_fit_is_rejected(torch):
                                                             "layout": "box2"}])
 
 
+def test_plan_over_l4_to_l7_sampled_against_oracle(torch):
+    """A slice of the serving stream (classes in {4..7}^4, K=3 per shell): every
+    integral finite, and the oracle on the quartets with the smallest total l
+    plus two random ones of total l <= 18."""
+    b = inputs.stream_batch(nq=200, seed=2106)
+    p = eri4.Plan(b.lq, b.nprim, b.kmax)
+    g = p.execute(dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    assert np.isfinite(g).all()
+    tot = b.lq.sum(axis=1)
+    small = np.flatnonzero(tot <= 18)
+    idx = sorted({*np.argsort(tot, kind="stable")[:3].tolist(),
+                  *np.random.default_rng(5).choice(small, 2, replace=False).tolist()})
+    check(g, p.offsets(), b, idx)
+
+
 def test_empty_plan(torch):
     p = eri4.Plan(np.zeros((0, 4), np.int32), np.zeros((0, 4), np.int32), 1)
     assert p.output_size == 0
