@@ -159,7 +159,8 @@ eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* 
 
 /*
  * Tile choices for plans (what an autotuner picks per class and contraction
- * size).  A tile is 16 * rows16 bra rows of one quartet; the Hermite integrals
+ * size).  A tile is 16 * rows16 bra rows of one quartet (rows16 = 4 only with
+ * the two box layouts and at most 16 ket column blocks, i.e. lc+ld <= 9); the Hermite integrals
  * of eq. (md1) live in LDS in one of three layouts:
  *   ERI4_LAYOUT_BOX   (L+1)^3 box, recursion in place            (L <= 24)
  *   ERI4_LAYOUT_SLAB  t-slabs, about half the space, in place      (L <= 28)
@@ -172,7 +173,7 @@ typedef enum { ERI4_LAYOUT_BOX = 0, ERI4_LAYOUT_SLAB = 1, ERI4_LAYOUT_BOX2 = 2 }
 typedef struct {
   int32_t l[4];           /* class (la lb|lc ld) */
   int32_t kq_min, kq_max; /* range of nprim[a]*nprim[b]*nprim[c]*nprim[d] */
-  int32_t rows16;         /* 1 or 2 */
+  int32_t rows16;         /* 1, 2 or 4 */
   int32_t layout;         /* eri4_layout */
 } eri4_tile_choice;
 

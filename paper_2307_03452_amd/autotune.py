@@ -23,10 +23,11 @@ DEFAULT_OUT = os.path.join(HERE, "tune_mi355x.json")
 
 # (kq_min, kq_max, K per shell used to time it)
 BUCKETS = [(1, 1, 1), (2, 40, 2), (41, 400, 3), (401, 4096, 5)]
-# timed batches hold at least this many 32-row tiles (two per compute unit),
-# so that the timing reflects the cost of a tile, not an idle GPU
+# timed batches hold at least this many of the largest (64-row) tiles, two per
+# compute unit, so that the timing reflects the cost of a tile, not an idle GPU
 MIN_TILES = 512
-CANDIDATES = [(2, "box2"), (1, "box2"), (2, "box"), (1, "box"), (2, "slab"), (1, "slab")]
+TILE_ROWS = 64
+CANDIDATES = [(4, "box2"), (2, "box2"), (1, "box2"), (4, "box"), (2, "box"), (1, "box"), (2, "slab"), (1, "slab")]
 
 
 def _time(plan, args, reps):
@@ -53,7 +54,7 @@ def tune(classes, reps=2, log=print):
     entries, timings = [], []
     for ci, ls in enumerate(classes):
         nab = ((ls[0] + 1) * (ls[0] + 2) // 2) * ((ls[1] + 1) * (ls[1] + 2) // 2)
-        nq = -(-MIN_TILES // -(-nab // 32))
+        nq = -(-MIN_TILES // -(-nab // TILE_ROWS))
         for kq_min, kq_max, k in BUCKETS:
             b = inputs.class_batch(ls, nq, k, seed=7000 + 17 * ci + k, exp_range=(0.05, 200.0))
             lq = np.tile(np.array(ls, np.int32), (nq, 1))

@@ -230,10 +230,11 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool s
 bool try_params(int la, int lb, int lc, int ld, int kmax, int rb, int lay, const DeviceState* d, int limit,
                 ClassParams* out) {
   const bool slab = lay == kLaySlab, two = lay == kLayBox2;
-  if ((rb != 1 && rb != 2) || lay < kLayBox || lay > kLayBox2) return false;
+  if ((rb != 1 && rb != 2 && rb != 4) || lay < kLayBox || lay > kLayBox2) return false;
+  if (rb == 4 && slab) return false;  // 64-row tiles are built for the box layouts
   if (two && la + lb + lc + ld > kBox2LMax) return false;
   ClassParams p = make_params(la, lb, lc, ld, kmax, rb, slab, two);
-  const int maxc = slab && rb == 1 ? kMaxC1 : 4;
+  const int maxc = rb == 4 ? 2 : (slab && rb == 1 ? kMaxC1 : 4);
   if (p.lds_bytes > limit || p.L > kMaxL || (p.nqb + 7) / 8 > maxc) return false;
   if (!slab && p.L > kBoxLMax) return false;  // the box recursion holds kRPerBox entries per thread
   p.rtab_off = d->rstart[(slab ? 1 : 0) * (kMaxL + 1) + p.L];
@@ -241,11 +242,11 @@ bool try_params(int la, int lb, int lc, int ld, int kmax, int rb, int lay, const
   return true;
 }
 
-// The library's own choice: the first that fits of two boxes (32-row tiles,
-// then 16), box, slab.
+// The library's own choice: the first that fits of two boxes (64-row tiles,
+// then 32, then 16), box (the same), slab (32, 16).
 bool pick_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, int limit, ClassParams* out) {
-  static const int order[6][2] = {{2, kLayBox2}, {1, kLayBox2}, {2, kLayBox},
-                                  {1, kLayBox},  {2, kLaySlab}, {1, kLaySlab}};
+  static const int order[8][2] = {{4, kLayBox2}, {2, kLayBox2}, {1, kLayBox2}, {4, kLayBox},
+                                  {2, kLayBox},  {1, kLayBox},  {2, kLaySlab}, {1, kLaySlab}};
   for (const auto& o : order)
     if (try_params(la, lb, lc, ld, kmax, o[0], o[1], d, limit, out)) return true;
   return false;
@@ -377,8 +378,8 @@ eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int
   std::vector<std::vector<int>> choices_of(8 * 8 * 8 * 8);
   for (int i = 0; i < nchoices; ++i) {
     const eri4_tile_choice& c = choices[i];
-    if (c.rows16 != 1 && c.rows16 != 2)
-      return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d: rows16 must be 1 or 2 (got %d)", i, c.rows16);
+    if (c.rows16 != 1 && c.rows16 != 2 && c.rows16 != 4)
+      return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d: rows16 must be 1, 2 or 4 (got %d)", i, c.rows16);
     if (c.layout < ERI4_LAYOUT_BOX || c.layout > ERI4_LAYOUT_BOX2)
       return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d: unknown layout %d", i, c.layout);
     if (c.kq_min > c.kq_max)

@@ -562,20 +562,29 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       build_etab(s.kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / s.kpair[0], s.kpair + 5, s.kpair + 8, true, lane);
     __syncthreads();
 
-    // second transform, written to HBM (accumulated over kl)
+    // second transform, written to HBM (accumulated over kl); groups of
+    // kGroup column blocks (2 with four row blocks, for the accumulators)
     const double unscale = s.kpair[12];
-    for (int g0 = 0; g0 < ncbw; g0 += kGroup) {
-      const int ng = min(kGroup, ncbw - g0);
+    constexpr int G2 = NR >= 4 ? 2 : kGroup;
+    for (int g0 = 0; g0 < ncbw; g0 += G2) {
+      const int ng = min(G2, ncbw - g0);
       const int cb0 = wave + 8 * g0;
       const bool first = kl == 0;
-      if (ng == 4)
-        gemm2_group<NR, 4, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
-      else if (ng == 3)
-        gemm2_group<NR, 3, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
-      else if (ng == 2)
-        gemm2_group<NR, 2, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
-      else
-        gemm2_group<NR, 1, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
+      if constexpr (G2 == 4) {
+        if (ng == 4)
+          gemm2_group<NR, 4, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
+        else if (ng == 3)
+          gemm2_group<NR, 3, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
+        else if (ng == 2)
+          gemm2_group<NR, 2, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
+        else
+          gemm2_group<NR, 1, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
+      } else {
+        if (ng == 2)
+          gemm2_group<NR, 2, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
+        else
+          gemm2_group<NR, 1, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
+      }
     }
     __syncthreads();
   }
@@ -640,7 +649,15 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
   const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                             // valid row blocks of this tile
 #define BODY(NR, NC1) fused_body<NR, NC1, LAY, F32>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane)
   constexpr int NR2 = RB >= 2 ? 2 : 1;
-  if (nrv == NR2 && NR2 == 2) {
+  if constexpr (RB == 4) {
+    // 64-row tiles (kets with at most 2 column blocks per wave): the last tile
+    // of a quartet runs with padding rows, whose outputs are not written
+    switch (nc1) {
+      case 0: BODY(4, 0); break;
+      case 1: BODY(4, 1); break;
+      default: BODY(4, 2); break;
+    }
+  } else if (nrv == NR2 && NR2 == 2) {
     switch (nc1) {
       case 0: BODY(NR2, 0); break;
       case 1: BODY(NR2, 1); break;
@@ -723,12 +740,16 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_plan_kernel(
       else
         process_tile<1, kLaySlab, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
     } else if (lay == kLayBox2) {
-      if (cp.rb == 2)
+      if (cp.rb == 4)
+        process_tile<4, kLayBox2, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+      else if (cp.rb == 2)
         process_tile<2, kLayBox2, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
       else
         process_tile<1, kLayBox2, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
     } else {
-      if (cp.rb == 2)
+      if (cp.rb == 4)
+        process_tile<4, kLayBox, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+      else if (cp.rb == 2)
         process_tile<2, kLayBox, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
       else
         process_tile<1, kLayBox, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);

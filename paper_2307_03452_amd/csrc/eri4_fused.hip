@@ -1,5 +1,6 @@
 // eri4_fused.hip -- the single-class fused kernels (FP64), one instance per
-// tile height (16 or 32 rows) and R layout (box, slab, two boxes).
+// tile height (16, 32 or, with a box layout, 64 rows) and R layout (box,
+// slab, two boxes).
 #include "eri4_device.h"
 
 namespace eri4 {
@@ -15,9 +16,10 @@ hipError_t launch_one(const ClassParams& p, dim3 grid, hipStream_t s, const Tabl
 }  // namespace
 
 hipError_t fused_set_attrs() {
-  const void* k[6] = {(const void*)eri4_fused_kernel<1, kLayBox>,  (const void*)eri4_fused_kernel<2, kLayBox>,
-                      (const void*)eri4_fused_kernel<1, kLaySlab>, (const void*)eri4_fused_kernel<2, kLaySlab>,
-                      (const void*)eri4_fused_kernel<1, kLayBox2>, (const void*)eri4_fused_kernel<2, kLayBox2>};
+  const void* k[8] = {(const void*)eri4_fused_kernel<1, kLayBox>,  (const void*)eri4_fused_kernel<2, kLayBox>,
+                      (const void*)eri4_fused_kernel<4, kLayBox>,  (const void*)eri4_fused_kernel<1, kLaySlab>,
+                      (const void*)eri4_fused_kernel<2, kLaySlab>, (const void*)eri4_fused_kernel<1, kLayBox2>,
+                      (const void*)eri4_fused_kernel<2, kLayBox2>, (const void*)eri4_fused_kernel<4, kLayBox2>};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
     if (e != hipSuccess) return e;
@@ -33,9 +35,11 @@ hipError_t fused_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Ta
       return two ? launch_one<2, kLaySlab>(p, grid, s, t, centers, exps, coefs, nprim, out, q0)
                  : launch_one<1, kLaySlab>(p, grid, s, t, centers, exps, coefs, nprim, out, q0);
     case kLayBox2:
+      if (p.rb == 4) return launch_one<4, kLayBox2>(p, grid, s, t, centers, exps, coefs, nprim, out, q0);
       return two ? launch_one<2, kLayBox2>(p, grid, s, t, centers, exps, coefs, nprim, out, q0)
                  : launch_one<1, kLayBox2>(p, grid, s, t, centers, exps, coefs, nprim, out, q0);
     default:
+      if (p.rb == 4) return launch_one<4, kLayBox>(p, grid, s, t, centers, exps, coefs, nprim, out, q0);
       return two ? launch_one<2, kLayBox>(p, grid, s, t, centers, exps, coefs, nprim, out, q0)
                  : launch_one<1, kLayBox>(p, grid, s, t, centers, exps, coefs, nprim, out, q0);
   }

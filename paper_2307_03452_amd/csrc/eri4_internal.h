@@ -99,7 +99,7 @@ struct ClassParams {
   int kmax;
   int rtab_off;        // first entry (uint2 units) of the recursion table for this layout and L
   int slab;            // R layout: 0 box, 1 slab
-  int rb;              // 16-row blocks per tile (1 or 2)
+  int rb;              // 16-row blocks per tile (1, 2, or 4 with a box layout)
   int lay;             // kLayBox, kLaySlab or kLayBox2 (slab == (lay == kLaySlab))
   int o_box1;          // kLayBox2: byte offset of the second R box
   // LDS layout (byte offsets)

@@ -129,6 +129,7 @@ def test_plan_create_tuned_rejects_bad_tile_tables_before_touching_a_device():
 
     good = {"l": (4, 4, 4, 4), "kq": (1, 1), "rows16": 2, "layout": "box2"}
     assert create([dict(good, rows16=3)]) == STATUS_INVALID and b"rows16" in L.eri4_last_error()
+    assert create([dict(good, rows16=8)]) == STATUS_INVALID and b"rows16" in L.eri4_last_error()
     assert create([dict(good, layout=7)]) == STATUS_INVALID and b"layout" in L.eri4_last_error()
     assert create([dict(good, kq=(5, 2))]) == STATUS_INVALID and b"kq_min" in L.eri4_last_error()
     assert create([dict(good, l=(4, 4, 8, 4))]) == STATUS_INVALID and b"angular momentum" in L.eri4_last_error()

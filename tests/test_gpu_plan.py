@@ -120,10 +120,12 @@ def test_tile_choices_give_the_default_results(torch):
     torch.cuda.synchronize()
     ref = ref.cpu().numpy()
     classes = sorted({tuple(int(x) for x in r) for r in b.lq})
-    for rows16, lay in ((1, "box"), (2, "box"), (1, "box2"), (2, "box2"), (1, "slab"), (2, "slab")):
-        # two boxes fit up to total order 19; other classes keep the default
+    for rows16, lay in ((1, "box"), (2, "box"), (4, "box"), (1, "box2"), (2, "box2"), (4, "box2"), (1, "slab"),
+                        (2, "slab")):
+        # two boxes fit up to total order 19 and 64-row tiles need kets with
+        # lc+ld <= 9; other classes keep the default
         tiles = [{"l": c, "kq": (1, 4096), "rows16": rows16, "layout": lay} for c in classes
-                 if lay != "box2" or sum(c) <= 19]
+                 if (lay != "box2" or sum(c) <= 19) and (rows16 != 4 or c[2] + c[3] <= 9)]
         p = eri4.Plan(b.lq, b.nprim, b.kmax, tiles=tiles)
         g = p.execute(C, E, Co)
         torch.cuda.synchronize()
