@@ -590,10 +590,6 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
   }
 }
 
-// ---------------------------------------------------------------------------
-// overlapped mode: one producer wave, kWaves-1 first-transform waves
-// ---------------------------------------------------------------------------
-
 // All the work of one tile: quartet q, bra rows rt*RB*16.., whose integrals
 // start at outq.  Called by every thread of the workgroup; ends with a barrier.
 template <int RB, int LAY, bool F32>
