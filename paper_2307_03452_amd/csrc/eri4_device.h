@@ -369,24 +369,54 @@ __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double*
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[r][c] = acc_zero<F32>();
   const int xs = cp.xs, nq4 = cp.nq4;
-  int pk = qtab[g].x;
-  for (int kk = 0; kk < nq4; kk += 4) {
+  auto load = [&](int kk, int pk, double (&aa)[NR], double (&xx)[NC], double (&yy)[NC], double (&zz)[NC]) {
     const int tq = pk & 0xff, uq = (pk >> 8) & 0xff, vq = (pk >> 16) & 0xff;
-    double a[NR], fx[NC], fy[NC], fz[NC];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) a[r] = X[(r * 16 + n) * xs + kk + g];
+    for (int r = 0; r < NR; ++r) aa[r] = X[(r * 16 + n) * xs + kk + g];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      fx[c] = kete[kx[c] + tq];
-      fy[c] = kete[ky[c] + uq];
-      fz[c] = kete[kz[c] + vq];
+      xx[c] = kete[kx[c] + tq];
+      yy[c] = kete[ky[c] + uq];
+      zz[c] = kete[kz[c] + vq];
     }
-    pk = qtab[min(kk + 4, nq4 - 4) + g].x;
+  };
+  auto step = [&](const double (&aa)[NR], const double (&xx)[NC], const double (&yy)[NC], const double (&zz)[NC]) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double b = fx[c] * fy[c] * fz[c];
+      const double b = xx[c] * yy[c] * zz[c];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r][c] = mfma16<F32>(a[r], b, acc[r][c]);
+      for (int r = 0; r < NR; ++r) acc[r][c] = mfma16<F32>(aa[r], b, acc[r][c]);
+    }
+  };
+  if constexpr (NR <= 2) {
+    // the operands of step k+4 are read before the MFMAs of step k are issued
+    // (measured: 1-2% on tiles of up to 32 rows; not kept for 64-row tiles,
+    // whose doubled operand registers cost more than it gains)
+    double a[NR], fx[NC], fy[NC], fz[NC];
+    load(0, qtab[g].x, a, fx, fy, fz);
+    int pk = qtab[min(4, nq4 - 4) + g].x;
+    for (int kk = 0; kk < nq4; kk += 4) {
+      double an[NR], fxn[NC], fyn[NC], fzn[NC];
+      load(min(kk + 4, nq4 - 4), pk, an, fxn, fyn, fzn);
+      pk = qtab[min(kk + 8, nq4 - 4) + g].x;
+      asm volatile("" ::: "memory");  // keep the prefetch ahead of the MFMAs
+      step(a, fx, fy, fz);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) a[r] = an[r];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        fx[c] = fxn[c];
+        fy[c] = fyn[c];
+        fz[c] = fzn[c];
+      }
+    }
+  } else {
+    int pk = qtab[g].x;
+    for (int kk = 0; kk < nq4; kk += 4) {
+      double a[NR], fx[NC], fy[NC], fz[NC];
+      load(kk, pk, a, fx, fy, fz);
+      pk = qtab[min(kk + 4, nq4 - 4) + g].x;
+      step(a, fx, fy, fz);
     }
   }
 #pragma unroll
