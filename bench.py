@@ -218,6 +218,36 @@ def time_classes_l7(reps=1):
     return out
 
 
+def time_low_l(nq=4096, reps=3):
+    """(dd|dd) and (ff|ff) at the paper's K = K_bra K_ket in {1, 5, 25}: one
+    eri4_batch call per case, inputs resident, 4096 quartets each."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs, metrics
+    d = lambda a: torch.from_numpy(a).cuda()
+    out = []
+    for l in (2, 3):
+        for K in (1, 5, 25):
+            b = inputs.low_l_batch(l, K, nq, seed=1100 + 10 * l + K)
+            C, E, Co, N = d(b.centers), d(b.exps), d(b.coefs), d(b.nprim)
+            o = eri4.batch(b.ls, C, E, Co, N)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                eri4.batch(b.ls, C, E, Co, N, out=o)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            ks = inputs.PAPER_K_SHELLS[K]
+            flops = nq * metrics.md4_flops(l, l, l, l, ks[0] * ks[1], ks[2] * ks[3])
+            ints = nq * metrics.integrals_per_quartet(l, l, l, l)
+            out.append({"class": "(%s%s|%s%s)" % ((("d", "f")[l - 2],) * 4), "K_bra_K_ket": K,
+                        "contraction_lengths": list(ks), "quartets": nq, "value": ints / t,
+                        "unit": "integrals/s", "ms_per_step": t * 1e3,
+                        "pct_fp64_peak": 100 * flops / t / 1e12 / FP64_PEAK_TFLOPS,
+                        "hbm_gb_per_s_output": nq * metrics.output_bytes(l, l, l, l) / t / 1e9})
+            del o
+    return out
+
+
 def time_stream(nq=50000, seed=1006, chunk=1024, ring=4):
     """Serving-style stream: 50 000 quartets over the 256 classes in {4..7}^4
     (Zipf counts, K=3 per shell) in chunks of 1024, each chunk a HIP graph
@@ -415,6 +445,7 @@ def main():
     if args.stream_steps > 0 and args.workload == "iiii_k1":
         rec["l7_classes"] = time_classes_l7()
         rec["stream"] = time_stream()
+        rec["low_l"] = time_low_l()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

@@ -99,11 +99,16 @@ def class_batch(ls, nq: int, K, seed: int, exp_range=(0.05, 50.0), box: float = 
                 kmax: int | None = None) -> Batch:
     """One class (la lb|lc ld), nq quartets.
 
-    K is an int (same contraction length for every shell) or a pair (lo, hi)
-    for a per-shell length drawn uniformly from lo..hi.
+    K is an int (same contraction length for every shell), a pair (lo, hi)
+    for a per-shell length drawn uniformly from lo..hi, or a dict
+    {"shells": (ka, kb, kc, kd)} for fixed lengths per shell position.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
-    if isinstance(K, (tuple, list)):
+    if isinstance(K, dict):
+        ks = np.array(K["shells"], dtype=np.int32)
+        nprim = np.tile(ks, (nq, 1))
+        km = int(ks.max())
+    elif isinstance(K, (tuple, list)):
         klo, khi = int(K[0]), int(K[1])
         nprim = rng.integers(klo, khi + 1, size=(nq, 4)).astype(np.int32)
         km = khi
@@ -115,7 +120,7 @@ def class_batch(ls, nq: int, K, seed: int, exp_range=(0.05, 50.0), box: float = 
     centers = rng.uniform(0.0, box, size=(nq, 4, 3))
     lo, hi = exp_range
     exps = np.exp(rng.uniform(np.log(lo), np.log(hi), size=(nq, 4, kmax)))
-    if km == 1 and not isinstance(K, (tuple, list)):
+    if km == 1 and isinstance(K, int):
         raw = np.ones((nq, 4, kmax))
     else:
         raw = rng.uniform(0.1, 1.0, size=(nq, 4, kmax))
@@ -145,6 +150,17 @@ def iiii(K: int = 1, nq: int = 512, seed: int | None = None) -> Batch:
     if seed is None:
         seed = 1002 if K == 1 else 1003
     return class_batch((6, 6, 6, 6), nq, K, seed, exp_range=(0.05, 200.0))
+
+
+# The paper's K for its low-l table is the product K_bra K_ket of the four
+# contraction lengths; read here as lengths (1,1,1,1), (5,1,1,1), (5,1,5,1).
+PAPER_K_SHELLS = {1: (1, 1, 1, 1), 5: (5, 1, 1, 1), 25: (5, 1, 5, 1)}
+
+
+def low_l_batch(l: int, K: int, nq: int, seed: int) -> Batch:
+    """(ll|ll) for l = 2 (d) or 3 (f) with the paper's K = K_bra K_ket in
+    {1, 5, 25}, exponents log-uniform [0.05, 50], 8-Bohr cube."""
+    return class_batch((l, l, l, l), nq, {"shells": PAPER_K_SHELLS[K]}, seed, exp_range=(0.05, 50.0))
 
 
 def stream_batch(nq: int = 50000, seed: int = 1006) -> Batch:

@@ -310,3 +310,13 @@ def test_maximum_contraction_length(torch):
         g = run_gpu(torch, b)
         o = oracle.eri_md4(b.ls, b.centers, b.exps, b.coefs, b.nprim)
         assert_quartets_close(g, o, label=b.ls)
+
+
+@pytest.mark.parametrize("l", [2, 3])
+@pytest.mark.parametrize("K", [1, 5, 25])
+def test_low_l_classes_at_the_papers_contraction_sizes(torch, l, K):
+    """(dd|dd) and (ff|ff) with K = K_bra K_ket in {1, 5, 25}."""
+    b = inputs.low_l_batch(l, K, 8, seed=300 + 10 * l + K)
+    g = run_gpu(torch, b)
+    o = oracle.eri_md4(b.ls, b.centers, b.exps, b.coefs, b.nprim)
+    assert_quartets_close(g, o, label=(l, K))
