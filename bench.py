@@ -248,6 +248,36 @@ def time_low_l(nq=4096, reps=3):
     return out
 
 
+def time_pairs(nbra=128, nket=128, kmax=3, reps=3):
+    """Bra list x ket list (eri4_plan_*_pairs): 128 x 128 shell pairs with l in
+    {4,5,6} per shell and contraction lengths 1..3, against the quartet plan
+    over the expanded batch (same quartets, per-quartet shell arrays)."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs
+    bra, ket = inputs.pair_list(nbra, 1201, kmax=kmax), inputs.pair_list(nket, 1202, kmax=kmax)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tiles = tuned_tiles()
+    pp = eri4.PairPlan(bra.l, bra.nprim, ket.l, ket.nprim, kmax, tiles=tiles)
+    args = (d(bra.centers), d(bra.exps), d(bra.coefs), d(ket.centers), d(ket.exps), d(ket.coefs))
+    out = pp.execute(*args)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pp.execute(*args, out=out)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    b = inputs.expand_pairs(bra, ket)
+    _, qout, tq = time_plan(b, "fp64", reps, 1, tiles)
+    flops = md4_flops_batch(b.lq, b.nprim)
+    return {"workload": "bra list x ket list: %d x %d shell pairs, l in {4,5,6} per shell, K per shell 1..%d"
+                        % (nbra, nket, kmax),
+            "quartets": b.nq, "value": pp.output_size / t, "unit": "integrals/s", "ms_per_step": t * 1e3,
+            "pct_fp64_peak": 100 * flops / t / 1e12 / FP64_PEAK_TFLOPS,
+            "quartet_plan_ms_per_step": tq * 1e3, "bitwise_equal_to_quartet_plan": bool(torch.equal(out, qout)),
+            "input_bytes": int(sum(a.numel() * 8 for a in args)),
+            "quartet_plan_input_bytes": int((b.centers.size + b.exps.size + b.coefs.size) * 8)}
+
+
 def time_stream(nq=50000, seed=1006, chunk=1024, ring=4):
     """Serving-style stream: 50 000 quartets over the 256 classes in {4..7}^4
     (Zipf counts, K=3 per shell) in chunks of 1024, each chunk a HIP graph
@@ -446,6 +476,7 @@ def main():
         rec["l7_classes"] = time_classes_l7()
         rec["stream"] = time_stream()
         rec["low_l"] = time_low_l()
+        rec["pairs"] = time_pairs()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

@@ -193,6 +193,35 @@ eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const doubl
 eri4_status eri4_plan_destroy(eri4_plan plan);
 
 /*
+ * Plans over a bra and a ket list of shell pairs: every bra pair with every
+ * ket pair, the way the paper's engine computes integrals for lists of bra and
+ * ket shell pairs (Sec. 3, library interface).  Quartet (i, j) is bra pair i
+ * with ket pair j, at index q = i * nket + j (bra-major); its block starts at
+ * offsets[q] (eri4_plan_output_offsets), as for quartet plans.
+ *
+ * eri4_plan_create_pairs reads the HOST arrays
+ *   bra_l, bra_nprim  int32 [nbra][2]   (la, lb) and contraction lengths of each bra pair
+ *   ket_l, ket_nprim  int32 [nket][2]   (lc, ld) and lengths of each ket pair
+ * (nbra * nket < 2^31) and otherwise behaves as eri4_plan_create_tuned
+ * (choices may be NULL with nchoices 0: the library picks the tiles).
+ *
+ * eri4_plan_execute_pairs takes DEVICE arrays per list:
+ *   bra_centers [nbra][2][3], bra_exponents / bra_coeffs [nbra][2][kmax],
+ *   ket_centers [nket][2][3], ket_exponents / ket_coeffs [nket][2][kmax]
+ * and reads each quartet's shells from them (nothing is expanded per quartet
+ * on the device).  Enqueue-only and capturable, as eri4_plan_execute.  A plan
+ * made from pair lists must be run with eri4_plan_execute_pairs and a quartet
+ * plan with eri4_plan_execute (INVALID_ARGUMENT otherwise).
+ */
+eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t* bra_l, const int32_t* bra_nprim,
+                                   int64_t nket, const int32_t* ket_l, const int32_t* ket_nprim, int kmax,
+                                   eri4_precision precision, const eri4_tile_choice* choices, int nchoices);
+eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, const double* bra_exponents,
+                                    const double* bra_coeffs, const double* ket_centers,
+                                    const double* ket_exponents, const double* ket_coeffs, double* out,
+                                    hipStream_t stream);
+
+/*
  * Stage entry points.  They run the same device code the fused eri4_batch
  * kernel runs for one stage, so each stage can be checked on its own.
  */

@@ -147,6 +147,8 @@ eri4_status set_attrs() {
   HIP_TRY(fused_set_attrs());
   HIP_TRY(plan_set_attrs_f64());
   HIP_TRY(plan_set_attrs_f32());
+  HIP_TRY(plan_set_attrs_f64p());
+  HIP_TRY(plan_set_attrs_f32p());
   HIP_TRY(hipFuncSetAttribute((const void*)hermite_r_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLdsBytes));
   return ERI4_SUCCESS;
@@ -323,6 +325,8 @@ struct eri4_plan_s {
   int lds_bytes = 0;
   int grid = 0;
   bool f32 = false;  // ERI4_PREC_FP32
+  bool pairs = false;  // made from a bra and a ket list of shell pairs
+  int64_t nbra = 0, nket = 0;
   int64_t out_size = 0;
   std::vector<int64_t> qoff;
   ClassParams* d_classes = nullptr;
@@ -350,10 +354,11 @@ eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* 
 static_assert(ERI4_LAYOUT_BOX == kLayBox && ERI4_LAYOUT_SLAB == kLaySlab && ERI4_LAYOUT_BOX2 == kLayBox2,
               "public and internal layout codes agree");
 
-eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
-                                   int kmax, eri4_precision precision, const eri4_tile_choice* choices,
-                                   int nchoices) {
-  g_err.clear();
+// Plan over quartets given by l / nprim; pairs: the shells will come from a
+// bra and a ket list (quartet q = bra pair q / nket with ket pair q % nket).
+static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim, int kmax,
+                               eri4_precision precision, const eri4_tile_choice* choices, int nchoices, bool pairs,
+                               int64_t nbra, int64_t nket) {
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
   *plan = nullptr;
   if (precision != ERI4_PREC_FP64 && precision != ERI4_PREC_FP32)
@@ -400,6 +405,9 @@ eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int
   p->nq = nquartets;
   p->kmax = kmax;
   p->f32 = precision == ERI4_PREC_FP32;
+  p->pairs = pairs;
+  p->nbra = nbra;
+  p->nket = nket;
 
   // groups of quartets with the same class and tile choice (the first matching
   // entry of the table, or none), keyed by class * (nchoices + 1) + entry + 1
@@ -480,8 +488,10 @@ eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int
 
   int ncu = 0, per_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
-  const hipError_t oe =
-      p->f32 ? plan_occupancy_f32(p->lds_bytes, &per_cu) : plan_occupancy_f64(p->lds_bytes, &per_cu);
+  const hipError_t oe = p->pairs ? (p->f32 ? plan_occupancy_f32p(p->lds_bytes, &per_cu)
+                                           : plan_occupancy_f64p(p->lds_bytes, &per_cu))
+                                 : (p->f32 ? plan_occupancy_f32(p->lds_bytes, &per_cu)
+                                           : plan_occupancy_f64(p->lds_bytes, &per_cu));
   if (oe != hipSuccess || per_cu < 1) per_cu = 1;
   p->grid = (int)std::min<int64_t>(std::max(p->nitems, 1), (int64_t)ncu * per_cu);
 
@@ -510,6 +520,13 @@ eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int
   return ERI4_SUCCESS;
 }
 
+eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
+                                   int kmax, eri4_precision precision, const eri4_tile_choice* choices,
+                                   int nchoices) {
+  g_err.clear();
+  return plan_create(plan, nquartets, l, nprim, kmax, precision, choices, nchoices, false, 0, 0);
+}
+
 int64_t eri4_plan_output_size(eri4_plan plan) { return plan ? plan->out_size : -1; }
 
 eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets) {
@@ -520,12 +537,11 @@ eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets) {
   return ERI4_SUCCESS;
 }
 
-eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents, const double* coeffs,
-                              double* out, hipStream_t stream) {
-  g_err.clear();
-  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
+// Enqueue the counter reset and the persistent kernel of a plan.
+static eri4_status plan_launch(eri4_plan plan, const Shells& shl, double* out, hipStream_t stream) {
   if (plan->nitems == 0) return ERI4_SUCCESS;
-  if (!centers || !exponents || !coeffs || !out) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  if (!shl.centers || !shl.exps || !shl.coefs || !out || (plan->pairs && (!shl.kcenters || !shl.kexps || !shl.kcoefs)))
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (dev != plan->device)
@@ -535,12 +551,64 @@ eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const doubl
   if (st != ERI4_SUCCESS) return st;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, plan->d_counter);
   HIP_TRY(hipGetLastError());
-  const PlanArgs a{plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter,
-                   centers, exponents, coeffs, out};
+  const PlanArgs a{plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter, shl,
+                   out};
   const Tables t{d->boys, d->rtab};
-  HIP_TRY(plan->f32 ? plan_launch_f32(dim3(plan->grid), plan->lds_bytes, stream, t, a)
-                    : plan_launch_f64(dim3(plan->grid), plan->lds_bytes, stream, t, a));
+  const dim3 grid(plan->grid);
+  if (plan->pairs)
+    HIP_TRY(plan->f32 ? plan_launch_f32p(grid, plan->lds_bytes, stream, t, a)
+                      : plan_launch_f64p(grid, plan->lds_bytes, stream, t, a));
+  else
+    HIP_TRY(plan->f32 ? plan_launch_f32(grid, plan->lds_bytes, stream, t, a)
+                      : plan_launch_f64(grid, plan->lds_bytes, stream, t, a));
   return ERI4_SUCCESS;
+}
+
+eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents, const double* coeffs,
+                              double* out, hipStream_t stream) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (plan->pairs)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan made from pair lists: use eri4_plan_execute_pairs");
+  return plan_launch(plan, Shells{centers, exponents, coeffs, nullptr, nullptr, nullptr, 0}, out, stream);
+}
+
+eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t* bra_l, const int32_t* bra_nprim,
+                                   int64_t nket, const int32_t* ket_l, const int32_t* ket_nprim, int kmax,
+                                   eri4_precision precision, const eri4_tile_choice* choices, int nchoices) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
+  *plan = nullptr;
+  if (nbra < 0 || nket < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "negative list length");
+  if (nbra > 0 && nket > (((int64_t)1 << 31) - 1) / nbra)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "nbra * nket must be below 2^31");
+  if ((nbra > 0 && (!bra_l || !bra_nprim)) || (nket > 0 && (!ket_l || !ket_nprim)))
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL host array");
+  // quartet (i, j) = bra pair i with ket pair j, at q = i * nket + j
+  const int64_t nq = nbra * nket;
+  std::vector<int32_t> l(4 * nq), np(4 * nq);
+  for (int64_t i = 0; i < nbra; ++i)
+    for (int64_t j = 0; j < nket; ++j) {
+      const int64_t q = i * nket + j;
+      l[4 * q] = bra_l[2 * i], l[4 * q + 1] = bra_l[2 * i + 1];
+      l[4 * q + 2] = ket_l[2 * j], l[4 * q + 3] = ket_l[2 * j + 1];
+      np[4 * q] = bra_nprim[2 * i], np[4 * q + 1] = bra_nprim[2 * i + 1];
+      np[4 * q + 2] = ket_nprim[2 * j], np[4 * q + 3] = ket_nprim[2 * j + 1];
+    }
+  return plan_create(plan, nq, l.data(), np.data(), kmax, precision, choices, nchoices, true, nbra, nket);
+}
+
+eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, const double* bra_exponents,
+                                    const double* bra_coeffs, const double* ket_centers,
+                                    const double* ket_exponents, const double* ket_coeffs, double* out,
+                                    hipStream_t stream) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (!plan->pairs) return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan made from quartets: use eri4_plan_execute");
+  return plan_launch(plan,
+                     Shells{bra_centers, bra_exponents, bra_coeffs, ket_centers, ket_exponents, ket_coeffs,
+                            plan->nket},
+                     out, stream);
 }
 
 eri4_status eri4_plan_destroy(eri4_plan plan) {

@@ -622,14 +622,20 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
 
 // All the work of one tile: quartet q, bra rows rt*RB*16.., whose integrals
 // start at outq.  Called by every thread of the workgroup; ends with a barrier.
-template <int RB, int LAY, bool F32>
+// Shells of quartet q: from per-quartet arrays (PAIRS false: centers
+// [q][4][3], exps/coefs [q][4][kmax]) or from a bra and a ket list of shell
+// pairs (PAIRS true: bra pair q / nket, ket pair q % nket, each list centers
+// [i][2][3], exps/coefs [i][2][kmax]; centers/exps/coefs are the bra list).
+template <int RB, int LAY, bool F32, bool PAIRS>
 __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned char* lds,
                                              const double* __restrict__ boys_tab,
                                              const uint2* __restrict__ rtab_L,
                                              const double* __restrict__ centers, const double* __restrict__ exps,
                                              const double* __restrict__ coefs, const int32_t* __restrict__ nprim,
                                              double* __restrict__ outq, int64_t q, int rt, int tid, int wave,
-                                             int lane) {
+                                             int lane, const double* __restrict__ kcenters,
+                                             const double* __restrict__ kexps, const double* __restrict__ kcoefs,
+                                             int64_t nket) {
   constexpr bool SLAB = LAY == kLaySlab;
   const int kmax = cp.kmax;
   Lds s;
@@ -647,14 +653,32 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
   s.kete = (double*)(lds + cp.o_kete);
   int* shn = (int*)(s.sh + 12 + 8 * kmax);
 
-  // shell data of this quartet
-  if (tid < 12) {
-    s.sh[tid] = centers[q * 12 + tid];
-  } else if (tid < 12 + 8 * kmax) {
-    const int j = tid - 12;
-    s.sh[tid] = (j < 4 * kmax) ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)];
-  } else if (tid >= 256 && tid < 260) {
-    shn[tid - 256] = nprim[q * 4 + (tid - 256)];
+  // shell data of this quartet: centres A B C D, then exponents and
+  // coefficients of shells a b c d (kmax each)
+  if constexpr (!PAIRS) {
+    if (tid < 12) {
+      s.sh[tid] = centers[q * 12 + tid];
+    } else if (tid < 12 + 8 * kmax) {
+      const int j = tid - 12;
+      s.sh[tid] = (j < 4 * kmax) ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)];
+    } else if (tid >= 256 && tid < 260) {
+      shn[tid - 256] = nprim[q * 4 + (tid - 256)];
+    }
+  } else {
+    const int64_t ib = q / nket, ik = q - ib * nket;
+    if (tid < 12) {
+      s.sh[tid] = tid < 6 ? centers[ib * 6 + tid] : kcenters[ik * 6 + (tid - 6)];
+    } else if (tid < 12 + 8 * kmax) {
+      const int j = tid - 12;
+      const bool ex = j < 4 * kmax;
+      const int jj = ex ? j : j - 4 * kmax;  // shell jj / kmax, primitive jj % kmax
+      if (jj < 2 * kmax)
+        s.sh[tid] = (ex ? exps : coefs)[ib * 2 * kmax + jj];
+      else
+        s.sh[tid] = (ex ? kexps : kcoefs)[ik * 2 * kmax + (jj - 2 * kmax)];
+    } else if (tid >= 256 && tid < 260) {
+      shn[tid - 256] = nprim[q * 4 + (tid - 256)];
+    }
   }
   build_htab(s.ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, SLAB, tid);
   build_htab(s.qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, SLAB, tid);
@@ -726,8 +750,9 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (SGPR)
   const int64_t q = q0 + blockIdx.x / cp.nrt;
   const int rt = blockIdx.x % cp.nrt;
-  process_tile<RB, LAY, false>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
-                         out + q * (int64_t)cp.nab * cp.ncd, q, rt, tid, wave, lane);
+  process_tile<RB, LAY, false, false>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
+                                      out + q * (int64_t)cp.nab * cp.ncd, q, rt, tid, wave, lane, nullptr,
+                                      nullptr, nullptr, 0);
 }
 
 // Persistent kernel for a plan: work items {quartet, row tile | class << 16},
@@ -735,13 +760,14 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
 // workgroup exits once the counter passes nitems).  qoff[q] is where quartet
 // q's integrals start in out.  Each class brings its own tile height and R
 // layout.  F32: both transforms on FP32 matrix cores (eri4_plan_create).
-template <bool F32>
+template <bool F32, bool PAIRS>
 __global__ __launch_bounds__(kThreads, 1) void eri4_plan_kernel(
     const ClassParams* __restrict__ classes, const int2* __restrict__ items, int nitems,
     const int64_t* __restrict__ qoff, const int32_t* __restrict__ nprim, int* __restrict__ counter,
     const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
     const double* __restrict__ centers, const double* __restrict__ exps,
-    const double* __restrict__ coefs, double* __restrict__ out) {
+    const double* __restrict__ coefs, double* __restrict__ out, const double* __restrict__ kcenters,
+    const double* __restrict__ kexps, const double* __restrict__ kcoefs, int64_t nket) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ int next_item;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -762,43 +788,53 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_plan_kernel(
     const int lay = cp.lay;
     if (lay == kLaySlab) {
       if (cp.rb == 2)
-        process_tile<2, kLaySlab, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<2, kLaySlab, F32, PAIRS>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave,
+                                              lane, kcenters, kexps, kcoefs, nket);
       else
-        process_tile<1, kLaySlab, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<1, kLaySlab, F32, PAIRS>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave,
+                                              lane, kcenters, kexps, kcoefs, nket);
     } else if (lay == kLayBox2) {
       if (cp.rb == 4)
-        process_tile<4, kLayBox2, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<4, kLayBox2, F32, PAIRS>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave,
+                                              lane, kcenters, kexps, kcoefs, nket);
       else if (cp.rb == 2)
-        process_tile<2, kLayBox2, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<2, kLayBox2, F32, PAIRS>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave,
+                                              lane, kcenters, kexps, kcoefs, nket);
       else
-        process_tile<1, kLayBox2, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<1, kLayBox2, F32, PAIRS>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave,
+                                              lane, kcenters, kexps, kcoefs, nket);
     } else {
       if (cp.rb == 4)
-        process_tile<4, kLayBox, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<4, kLayBox, F32, PAIRS>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave,
+                                              lane, kcenters, kexps, kcoefs, nket);
       else if (cp.rb == 2)
-        process_tile<2, kLayBox, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<2, kLayBox, F32, PAIRS>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave,
+                                              lane, kcenters, kexps, kcoefs, nket);
       else
-        process_tile<1, kLayBox, F32>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, lane);
+        process_tile<1, kLayBox, F32, PAIRS>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave,
+                                              lane, kcenters, kexps, kcoefs, nket);
     }
   }
 }
 
-template <bool F32>
+template <bool F32, bool PAIRS>
 hipError_t plan_set_attrs_t() {
-  return hipFuncSetAttribute((const void*)eri4_plan_kernel<F32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute((const void*)eri4_plan_kernel<F32, PAIRS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              kMaxLdsBytes - 64);
 }
 
-template <bool F32>
+template <bool F32, bool PAIRS>
 hipError_t plan_occupancy_t(int lds_bytes, int* per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void*)eri4_plan_kernel<F32>, kThreads,
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void*)eri4_plan_kernel<F32, PAIRS>, kThreads,
                                                       lds_bytes);
 }
 
-template <bool F32>
+template <bool F32, bool PAIRS>
 hipError_t plan_launch_t(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a) {
-  hipLaunchKernelGGL(eri4_plan_kernel<F32>, grid, dim3(kThreads), lds_bytes, s, a.classes, a.items, a.nitems,
-                     a.qoff, a.nprim, a.counter, t.boys, t.rtab, a.centers, a.exps, a.coefs, a.out);
+  const Shells& h = a.shells;
+  hipLaunchKernelGGL((eri4_plan_kernel<F32, PAIRS>), grid, dim3(kThreads), lds_bytes, s, a.classes, a.items,
+                     a.nitems, a.qoff, a.nprim, a.counter, t.boys, t.rtab, h.centers, h.exps, h.coefs, a.out,
+                     h.kcenters, h.kexps, h.kcoefs, h.nket);
   return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // eri4_launch.h -- host-side entry points to the kernels of liberi4 that are
-// compiled in their own translation units (eri4_fused.hip, eri4_plan64.hip,
-// eri4_plan32.hip).  Not part of the public ABI.
+// compiled in their own translation units (eri4_fused.hip and the four
+// eri4_plan*.hip).  Not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -20,7 +20,22 @@ hipError_t fused_set_attrs();
 hipError_t fused_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
                         const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0);
 
-// The persistent plan kernel, with FP64 or FP32 transforms.
+// Where the shells of quartet q come from: per-quartet arrays (nket == 0:
+// centers [q][4][3], exps/coefs [q][4][kmax]), or a bra and a ket list of
+// shell pairs (quartet q = bra pair q / nket with ket pair q % nket; each list
+// centers [i][2][3], exps/coefs [i][2][kmax]).
+struct Shells {
+  const double* centers;  // quartets, or bra pairs
+  const double* exps;
+  const double* coefs;
+  const double* kcenters;  // ket pairs (nket > 0)
+  const double* kexps;
+  const double* kcoefs;
+  int64_t nket;
+};
+
+// The persistent plan kernel, with FP64 or FP32 transforms (f64 / f32), shells
+// from per-quartet arrays or, with the suffix p, from pair lists.
 struct PlanArgs {
   const ClassParams* classes;
   const int2* items;
@@ -28,16 +43,17 @@ struct PlanArgs {
   const int64_t* qoff;
   const int32_t* nprim;
   int* counter;
-  const double* centers;
-  const double* exps;
-  const double* coefs;
+  Shells shells;
   double* out;
 };
-hipError_t plan_set_attrs_f64();
-hipError_t plan_set_attrs_f32();
-hipError_t plan_occupancy_f64(int lds_bytes, int* per_cu);
-hipError_t plan_occupancy_f32(int lds_bytes, int* per_cu);
-hipError_t plan_launch_f64(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a);
-hipError_t plan_launch_f32(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a);
+#define ERI4_PLAN_KERNEL_ENTRIES(sfx)                                                                   \
+  hipError_t plan_set_attrs_##sfx();                                                                   \
+  hipError_t plan_occupancy_##sfx(int lds_bytes, int* per_cu);                                         \
+  hipError_t plan_launch_##sfx(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a);
+ERI4_PLAN_KERNEL_ENTRIES(f64)
+ERI4_PLAN_KERNEL_ENTRIES(f32)
+ERI4_PLAN_KERNEL_ENTRIES(f64p)
+ERI4_PLAN_KERNEL_ENTRIES(f32p)
+#undef ERI4_PLAN_KERNEL_ENTRIES
 
 }  // namespace eri4

@@ -1,10 +1,12 @@
-// eri4_plan64.hip -- the persistent plan kernel with FP64 transforms.
+// eri4_plan64.hip -- the persistent plan kernel with FP64 transforms, shells read from per-quartet arrays.
 #include "eri4_device.h"
 
 namespace eri4 {
-hipError_t plan_set_attrs_f64() { return plan_set_attrs_t<false>(); }
-hipError_t plan_occupancy_f64(int lds_bytes, int* per_cu) { return plan_occupancy_t<false>(lds_bytes, per_cu); }
+hipError_t plan_set_attrs_f64() { return plan_set_attrs_t<false, false>(); }
+hipError_t plan_occupancy_f64(int lds_bytes, int* per_cu) {
+  return plan_occupancy_t<false, false>(lds_bytes, per_cu);
+}
 hipError_t plan_launch_f64(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a) {
-  return plan_launch_t<false>(grid, lds_bytes, s, t, a);
+  return plan_launch_t<false, false>(grid, lds_bytes, s, t, a);
 }
 }  // namespace eri4

@@ -47,7 +47,8 @@ STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UN
 # every symbol include/eri4.h declares
 EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version", "eri4_init",
            "eri4_batch", "eri4_plan_create", "eri4_plan_create_tuned", "eri4_plan_output_size", "eri4_plan_output_offsets",
-           "eri4_plan_execute", "eri4_plan_destroy", "eri4_boys", "eri4_hermite_r", "eri4_hermite_e")
+           "eri4_plan_execute", "eri4_plan_destroy", "eri4_plan_create_pairs", "eri4_plan_execute_pairs",
+           "eri4_boys", "eri4_hermite_r", "eri4_hermite_e")
 
 _lib = None
 
@@ -88,6 +89,10 @@ def lib() -> ctypes.CDLL:
         L.eri4_plan_execute.restype = c_int
         L.eri4_plan_destroy.argtypes = [vp]
         L.eri4_plan_destroy.restype = c_int
+        L.eri4_plan_create_pairs.argtypes = [ctypes.POINTER(vp), i64, vp, vp, i64, vp, vp, c_int, c_int, vp, c_int]
+        L.eri4_plan_create_pairs.restype = c_int
+        L.eri4_plan_execute_pairs.argtypes = [vp] * 9
+        L.eri4_plan_execute_pairs.restype = c_int
         L.eri4_boys.argtypes = [c_int, i64, vp, vp, vp]
         L.eri4_boys.restype = c_int
         L.eri4_hermite_r.argtypes = [c_int, i64, vp, vp, vp, vp, vp, vp]
@@ -245,3 +250,47 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+class PairPlan(Plan):
+    """Every bra shell pair with every ket shell pair (eri4_plan_*_pairs).
+
+    bra_l, bra_nprim: host int32 [nbra, 2]; ket_l, ket_nprim: host int32 [nket, 2].
+    Quartet (i, j) is bra pair i with ket pair j, at index q = i * nket + j of
+    offsets().  execute() takes the device lists: centers float64 [n, 2, 3],
+    exps / coefs float64 [n, 2, kmax] for the bra and the ket side.
+    """
+
+    def __init__(self, bra_l, bra_nprim, ket_l, ket_nprim, kmax: int, precision: str = "fp64", tiles=None):
+        import numpy as np
+        bl, bn = (np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 2) for a in (bra_l, bra_nprim))
+        kl, kn = (np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 2) for a in (ket_l, ket_nprim))
+        assert bl.shape == bn.shape and kl.shape == kn.shape
+        self.nbra, self.nket = bl.shape[0], kl.shape[0]
+        self.nq = self.nbra * self.nket
+        self.kmax = int(kmax)
+        self.precision = precision
+        h = ctypes.c_void_p()
+        arr = tile_choices(tiles) if tiles else None
+        vp = ctypes.c_void_p
+        _check(lib().eri4_plan_create_pairs(
+            ctypes.byref(h), self.nbra, bl.ctypes.data_as(vp), bn.ctypes.data_as(vp), self.nket,
+            kl.ctypes.data_as(vp), kn.ctypes.data_as(vp), self.kmax,
+            PRECISION[precision] if isinstance(precision, str) else int(precision),
+            ctypes.cast(arr, vp) if arr is not None else None, len(arr) if arr is not None else 0))
+        self._h = h
+
+    def execute(self, bra_centers, bra_exps, bra_coefs, ket_centers, ket_exps, ket_coefs, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.output_size, dtype=torch.float64, device=bra_centers.device)
+        if out.numel() < self.output_size:
+            raise ValueError("output buffer too small")
+        for c, e, w, n in ((bra_centers, bra_exps, bra_coefs, self.nbra), (ket_centers, ket_exps, ket_coefs, self.nket)):
+            if tuple(c.shape) != (n, 2, 3) or tuple(e.shape) != (n, 2, self.kmax) or tuple(w.shape) != (n, 2, self.kmax):
+                raise ValueError("pair lists do not match the plan")
+        _check(lib().eri4_plan_execute_pairs(
+            self._h, _ptr(bra_centers, "float64"), _ptr(bra_exps, "float64"), _ptr(bra_coefs, "float64"),
+            _ptr(ket_centers, "float64"), _ptr(ket_exps, "float64"), _ptr(ket_coefs, "float64"),
+            _ptr(out, "float64"), _stream(stream)))
+        return out

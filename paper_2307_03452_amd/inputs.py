@@ -200,3 +200,45 @@ def uneven_batch(nq: int = 20000, seed: int = 1004, lvals=(4, 5, 6), kmax: int =
     raw = np.where(nprim[..., None] == 1, 1.0, raw)
     coefs = normalize_shells(lq, exps, raw, nprim)
     return Batch(None, centers, exps, coefs, nprim, lq)
+
+
+@dataclass
+class PairList:
+    """A list of shell pairs (one side of a bra-list x ket-list batch).
+
+    l, nprim  int32 [n][2]; centers float64 [n][2][3]; exps, coefs float64 [n][2][kmax]."""
+    l: np.ndarray
+    nprim: np.ndarray
+    centers: np.ndarray
+    exps: np.ndarray
+    coefs: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return self.l.shape[0]
+
+
+def pair_list(n: int, seed: int, lvals=(4, 5, 6), kmax: int = 4, exp_range=(0.05, 200.0),
+              box: float = 8.0) -> PairList:
+    """n shell pairs, each shell's l uniform over lvals and contraction length
+    uniform in 1..kmax; centres, exponents and coefficients as in uneven_batch."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    l = rng.choice(np.asarray(lvals, dtype=np.int32), size=(n, 2)).astype(np.int32)
+    nprim = rng.integers(1, kmax + 1, size=(n, 2)).astype(np.int32)
+    centers = rng.uniform(0.0, box, size=(n, 2, 3))
+    lo, hi = exp_range
+    exps = np.exp(rng.uniform(np.log(lo), np.log(hi), size=(n, 2, kmax)))
+    raw = rng.uniform(0.1, 1.0, size=(n, 2, kmax))
+    raw = np.where(nprim[..., None] == 1, 1.0, raw)
+    coefs = normalize_shells(l, exps, raw, nprim)
+    return PairList(l, nprim, centers, exps, coefs)
+
+
+def expand_pairs(bra: PairList, ket: PairList) -> Batch:
+    """The quartet batch of every bra pair with every ket pair, quartet
+    (i, j) at index i * ket.n + j (shells a, b from bra pair i; c, d from ket
+    pair j).  Both lists must have the same kmax."""
+    nb, nk = bra.n, ket.n
+    cat = lambda x, y: np.concatenate([np.repeat(x, nk, axis=0), np.tile(y, (nb,) + (1,) * (y.ndim - 1))], axis=1)
+    return Batch(None, cat(bra.centers, ket.centers), cat(bra.exps, ket.exps), cat(bra.coefs, ket.coefs),
+                 cat(bra.nprim, ket.nprim).astype(np.int32), cat(bra.l, ket.l).astype(np.int32))

@@ -138,6 +138,49 @@ def test_plan_create_tuned_rejects_bad_tile_tables_before_touching_a_device():
     assert h.value is None
 
 
+def test_plan_create_pairs_rejects_bad_host_arrays_before_touching_a_device():
+    import numpy as np
+    L = eri4.lib()
+    h = ctypes.c_void_p()
+    bl, bn = np.full((3, 2), 4, np.int32), np.ones((3, 2), np.int32)
+    kl, kn = np.full((2, 2), 5, np.int32), np.ones((2, 2), np.int32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+
+    def create(nbra=3, bl=bl, bn=bn, nket=2, kl=kl, kn=kn, kmax=1, prec=0, plan=True):
+        return L.eri4_plan_create_pairs(ctypes.byref(h) if plan else None, nbra, ptr(bl) if bl is not None else None,
+                                        ptr(bn), nket, ptr(kl) if kl is not None else None, ptr(kn), kmax, prec,
+                                        None, 0)
+
+    assert create(plan=False) == STATUS_INVALID
+    assert create(nbra=-1) == STATUS_INVALID and b"negative" in L.eri4_last_error()
+    assert create(nbra=1 << 16, nket=1 << 16) == STATUS_INVALID and b"2^31" in L.eri4_last_error()
+    assert create(bl=None) == STATUS_INVALID and b"NULL" in L.eri4_last_error()
+    assert create(kl=None) == STATUS_INVALID
+    bad = kl.copy(); bad[1, 0] = 8
+    assert create(kl=bad) == STATUS_UNSUPPORTED
+    badn = bn.copy(); badn[2, 1] = 3
+    assert create(bn=badn, kmax=2) == STATUS_INVALID and b"contraction length" in L.eri4_last_error()
+    assert create(prec=5) == STATUS_INVALID and b"precision" in L.eri4_last_error()
+    assert h.value is None
+    assert L.eri4_plan_execute_pairs(None, None, None, None, None, None, None, None, None) == STATUS_INVALID
+
+
+def test_pair_list_expansion_is_bra_major():
+    import numpy as np
+    from paper_2307_03452_amd import inputs
+    bra, ket = inputs.pair_list(3, 11, kmax=3), inputs.pair_list(4, 12, kmax=3)
+    b = inputs.expand_pairs(bra, ket)
+    assert b.nq == 12 and b.lq.shape == (12, 4) and b.exps.shape == (12, 4, 3)
+    for i in range(3):
+        for j in range(4):
+            q = i * 4 + j
+            assert np.array_equal(b.lq[q], np.r_[bra.l[i], ket.l[j]])
+            assert np.array_equal(b.nprim[q], np.r_[bra.nprim[i], ket.nprim[j]])
+            assert np.array_equal(b.centers[q], np.r_[bra.centers[i], ket.centers[j]])
+            assert np.array_equal(b.coefs[q], np.r_[bra.coefs[i], ket.coefs[j]])
+    assert set(np.unique(bra.l)) <= {4, 5, 6} and bra.nprim.min() >= 1 and bra.nprim.max() <= 3
+
+
 def test_uneven_batch_recipe():
     import numpy as np
     from paper_2307_03452_amd import inputs

@@ -1,0 +1,115 @@
+"""Plans over a bra and a ket list of shell pairs (eri4_plan_*_pairs): the
+integrals equal, bit for bit, those of the quartet plan over the expanded
+batch, and the oracle's on sampled quartets."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03452_amd import eri4, inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+ZERO_SCALE = 1e-250
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    eri4.init()
+    return _t
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def lists(torch, pl):
+    return dev(torch, pl.centers), dev(torch, pl.exps), dev(torch, pl.coefs)
+
+
+def run_pairs(torch, bra, ket, precision="fp64"):
+    p = eri4.PairPlan(bra.l, bra.nprim, ket.l, ket.nprim, bra.exps.shape[2], precision)
+    out = p.execute(*lists(torch, bra), *lists(torch, ket))
+    torch.cuda.synchronize()
+    return p, out.cpu().numpy()
+
+
+def run_quartets(torch, b, precision="fp64"):
+    p = eri4.Plan(b.lq, b.nprim, b.kmax, precision)
+    out = p.execute(dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs))
+    torch.cuda.synchronize()
+    return p, out.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pair_plan_equals_expanded_quartet_plan_bitwise(torch, precision):
+    bra, ket = inputs.pair_list(7, 31, kmax=3), inputs.pair_list(9, 32, kmax=3)
+    pp, g = run_pairs(torch, bra, ket, precision)
+    b = inputs.expand_pairs(bra, ket)
+    qp, ref = run_quartets(torch, b, precision)
+    assert pp.nq == b.nq == 63 and pp.output_size == qp.output_size
+    assert np.array_equal(pp.offsets(), qp.offsets())
+    assert np.array_equal(g, ref)
+
+
+def test_pair_plan_against_oracle(torch):
+    """Low l (every quartet) and high l (sampled quartets, including the
+    first and last of the bra-major order)."""
+    for lvals, nb, nk, seed, sample in (((0, 1, 2, 3), 5, 6, 33, None), ((4, 5, 6), 4, 5, 35, 6)):
+        bra = inputs.pair_list(nb, seed, lvals=lvals, kmax=3)
+        ket = inputs.pair_list(nk, seed + 1, lvals=lvals, kmax=3)
+        p, g = run_pairs(torch, bra, ket)
+        b = inputs.expand_pairs(bra, ket)
+        off = p.offsets()
+        idx = range(b.nq) if sample is None else sorted(
+            {0, b.nq - 1, *np.random.default_rng(seed).choice(b.nq, sample, replace=False).tolist()})
+        for q in idx:
+            s = inputs.subset(b, [q])
+            ref = oracle.eri_md4(tuple(int(x) for x in b.lq[q]), s.centers, s.exps, s.coefs, s.nprim)[0]
+            got = g[off[q]:off[q] + ref.size].reshape(ref.shape)
+            scale = max(np.abs(ref).max(), ZERO_SCALE)
+            assert np.abs(got - ref).max() <= TOL * scale, (q, tuple(b.lq[q]))
+
+
+def test_pair_plan_with_tuned_tiles(torch):
+    """A tile table routes pair quartets like quartet-plan ones; results do not
+    change with the tiling."""
+    bra = inputs.pair_list(3, 37, lvals=(4, 5), kmax=2)
+    ket = inputs.pair_list(4, 38, lvals=(4, 5), kmax=2)
+    _, ref = run_pairs(torch, bra, ket)
+    tiles = [{"l": (la, lb, lc, ld), "kq": (1, 16), "rows16": 1, "layout": "box"}
+             for la in (4, 5) for lb in (4, 5) for lc in (4, 5) for ld in (4, 5)]
+    p = eri4.PairPlan(bra.l, bra.nprim, ket.l, ket.nprim, 2, tiles=tiles)
+    g = p.execute(*lists(torch, bra), *lists(torch, ket))
+    torch.cuda.synchronize()
+    b = inputs.expand_pairs(bra, ket)
+    scale = np.abs(ref).max()
+    assert np.abs(g.cpu().numpy() - ref).max() <= TOL * scale
+    assert b.nq == p.nq
+
+
+def test_pair_and_quartet_plans_refuse_each_others_execute(torch):
+    bra, ket = inputs.pair_list(2, 39, kmax=1), inputs.pair_list(2, 40, kmax=1)
+    pp = eri4.PairPlan(bra.l, bra.nprim, ket.l, ket.nprim, 1)
+    b = inputs.expand_pairs(bra, ket)
+    qp = eri4.Plan(b.lq, b.nprim, 1)
+    L = eri4.lib()
+    C, E, Co = dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs)
+    out = torch.zeros(qp.output_size, dtype=torch.float64, device="cuda")
+    p = lambda t: t.data_ptr()
+    assert L.eri4_plan_execute(pp._h, p(C), p(E), p(Co), p(out), None) == 1
+    assert b"pair lists" in L.eri4_last_error()
+    assert L.eri4_plan_execute_pairs(qp._h, p(C), p(E), p(Co), p(C), p(E), p(Co), p(out), None) == 1
+    assert b"quartets" in L.eri4_last_error()
+
+
+def test_empty_pair_lists(torch):
+    bra = inputs.pair_list(3, 41, kmax=1)
+    for nb, nk in ((3, 0), (0, 3), (0, 0)):
+        p = eri4.PairPlan(bra.l[:nb], bra.nprim[:nb], bra.l[:nk], bra.nprim[:nk], 1)
+        assert p.nq == 0 and p.output_size == 0
+        z = lambda n, k: torch.zeros(n, 2, k, dtype=torch.float64, device="cuda")
+        p.execute(z(nb, 3), z(nb, 1), z(nb, 1), z(nk, 3), z(nk, 1), z(nk, 1),
+                  out=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
