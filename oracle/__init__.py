@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark are its only users.  It shares no code with the HIP
 library.  See ``eri4_oracle.c`` for the schemes it implements and the readings
-of the paper it takes.
+of the paper it takes, and ``solid.py`` for the Cartesian to solid-harmonic
+transform.
 """
 import ctypes
 import os
