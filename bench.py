@@ -278,6 +278,44 @@ def time_pairs(nbra=128, nket=128, kmax=3, reps=3):
             "quartet_plan_input_bytes": int((b.centers.size + b.exps.size + b.coefs.size) * 8)}
 
 
+def time_solid(reps=3):
+    """Solid-harmonic output (eri4_batch_solid, FP64): (ii|ii) K=1 on the
+    512-quartet batch and K=5 per shell on its first 128 quartets.  FLOPs are
+    the two transforms over solid functions, 2 Sab (Kb Np)(Kk Nq) + 2 Sab (Kk Nq) Scd
+    per quartet; the time includes building the H matrices."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs, metrics
+    from oracle import solid
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = []
+    for K, nq in ((1, 512), (5, 128)):
+        b = inputs.subset(inputs.iiii(K=K), range(nq))
+        C, E, Co, N = d(b.centers), d(b.exps), d(b.coefs), d(b.nprim)
+        work = torch.empty(eri4.solid_work_size(b.ls, b.kmax, nq), dtype=torch.float64, device="cuda")
+        o = eri4.batch_solid(b.ls, C, E, Co, N, work=work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eri4.batch_solid(b.ls, C, E, Co, N, work=work, out=o)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        flops = nq * metrics.md4_flops(6, 6, 6, 6, K * K, K * K, solid=True)
+        # parity: two quartets against the oracle, relative to the scale the
+        # transform rounds at, max sum_k |C x C x C x C|[m, k] |cart[k]|
+        import oracle
+        cart = oracle.eri_md4(b.ls, b.centers[:2], b.exps[:2], b.coefs[:2], b.nprim[:2])
+        ref = solid.cart_to_solid(cart, b.ls)
+        bound = solid.cart_to_solid(np.abs(cart), b.ls, absolute=True)
+        g = o[:2].cpu().numpy()
+        err = max(float(np.abs(g[i] - ref[i]).max() / bound[i].max()) for i in range(2))
+        out.append({"workload": "(ii|ii) solid harmonics, K=%d per shell, %d quartets" % (K, nq),
+                    "value": nq * 13 ** 4 / t, "unit": "integrals/s", "ms_per_step": t * 1e3,
+                    "pct_fp64_peak": 100 * flops / t / 1e12 / FP64_PEAK_TFLOPS,
+                    "workspace_bytes": work.numel() * 8, "parity_max_err_2q_rel_transform_bound": err})
+        del work, o
+    return out
+
+
 def time_stream(nq=50000, seed=1006, chunk=1024, ring=4):
     """Serving-style stream: 50 000 quartets over the 256 classes in {4..7}^4
     (Zipf counts, K=3 per shell) in chunks of 1024, each chunk a HIP graph
@@ -477,6 +515,7 @@ def main():
         rec["stream"] = time_stream()
         rec["low_l"] = time_low_l()
         rec["pairs"] = time_pairs()
+        rec["solid"] = time_solid()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

@@ -121,6 +121,41 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets,
                        const int32_t* nprim, int kmax, double* out, hipStream_t stream);
 
 /*
+ * Solid-harmonic output.  The paper contracts the E matrices with the
+ * coefficients of real solid-harmonic Gaussians in Cartesian ones before the
+ * transforms, H_ab^p = sum_a C_a sum_b C_b E_ab^p (Sec. 2, the equation defining
+ * H, coefficients after Schlegel and Frisch), so that both transforms run over
+ * the 2l+1 solid functions of each shell instead of the (l+1)(l+2)/2 Cartesian
+ * ones.
+ *
+ * Convention: functions m = -l..l; m > 0 the real part of (x + i y)^m times a
+ * polynomial in z and r^2, m < 0 the imaginary part of (x + i y)^|m| times the
+ * same polynomial, no Condon-Shortley phase, unit norm when the Cartesian
+ * components share the coefficient that normalises x^l (as the inputs'
+ * coefficients do).  For l = 1 the order is (y, z, x).
+ *
+ * eri4_solid_coefficients writes C for shell l (0..ERI4_MAX_L) into the HOST
+ * array C[2l+1][(l+1)(l+2)/2] (rows m = -l..l, columns in the Cartesian order
+ * of eri4_batch).
+ *
+ * eri4_batch_solid computes the integrals of eri4_batch over solid harmonics:
+ *   out  device double [nquartets][2la+1][2lb+1][2lc+1][2ld+1], row-major
+ *   work device double [work_size], scratch owned by the caller for the H
+ *        matrices of every primitive pair; contents on entry are ignored and
+ *        undefined on return
+ * Other arguments as eri4_batch.  The quartets run in passes of as many as the
+ * workspace holds: eri4_solid_work_size(la, lb, lc, ld, kmax, n) doubles hold
+ * n quartets (-1 for bad arguments); a workspace below one quartet's size gives
+ * INVALID_ARGUMENT.  FP64 throughout; enqueue-only (nothing is allocated
+ * after the first call on a device).
+ */
+eri4_status eri4_solid_coefficients(int l, double* C);
+int64_t eri4_solid_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets);
+eri4_status eri4_batch_solid(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                             const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                             double* work, int64_t work_size, double* out, hipStream_t stream);
+
+/*
  * Plans -- one batch mixing classes and contraction lengths, computed by a single
  * persistent launch (Sec. 3, batched evaluation; the paper groups shell pairs of
  * equal total angular momentum and contraction order into lists, here the

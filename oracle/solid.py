@@ -91,13 +91,15 @@ def solid_matrix(l: int) -> np.ndarray:
     return C
 
 
-def cart_to_solid(block: np.ndarray, ls) -> np.ndarray:
+def cart_to_solid(block: np.ndarray, ls, absolute: bool = False) -> np.ndarray:
     """Solid-harmonic integrals from Cartesian ones.
 
     block: [..., Na, Nb, Nc, Nd] over the Cartesian components of shells
-    l = ls; returns [..., 2la+1, 2lb+1, 2lc+1, 2ld+1]."""
+    l = ls; returns [..., 2la+1, 2lb+1, 2lc+1, 2ld+1].  absolute=True applies
+    |C| instead of C: given |block| that is sum_k |C x C x C x C|[m, k] |block[k]|,
+    the magnitude that bounds the rounding error of the transform."""
     la, lb, lc, ld = (int(x) for x in ls)
-    Ca, Cb, Cc, Cd = (solid_matrix(l) for l in (la, lb, lc, ld))
+    Ca, Cb, Cc, Cd = (np.abs(solid_matrix(l)) if absolute else solid_matrix(l) for l in (la, lb, lc, ld))
     x = np.tensordot(block, Cd, axes=([-1], [1]))                   # [..., a, b, c, md]
     x = np.moveaxis(np.tensordot(x, Cc, axes=([-2], [1])), -1, -2)  # [..., a, b, mc, md]
     x = np.moveaxis(np.tensordot(x, Cb, axes=([-3], [1])), -1, -3)  # [..., a, mb, mc, md]

@@ -26,6 +26,8 @@
 namespace eri4 {
 void make_boys_table(std::vector<double>& tab);
 void make_rtabs(std::vector<uint32_t>& tab, std::vector<int>& start);
+void make_solid_table(std::vector<double>& tab);
+void solid_dense(int l, double* C);
 
 __global__ void reset_counter_kernel(int* counter) {
   if (threadIdx.x == 0) counter[0] = 0;
@@ -131,6 +133,7 @@ struct DeviceState {
   bool ready = false;
   double* boys = nullptr;
   uint2* rtab = nullptr;
+  double* stab = nullptr;  // solid-harmonic coefficients (make_solid_table)
   int rstart[2 * (kMaxL + 1)] = {0};  // [layout][L], in uint2 entries
 };
 
@@ -145,6 +148,7 @@ std::vector<DeviceState> g_dev;
 
 eri4_status set_attrs() {
   HIP_TRY(fused_set_attrs());
+  HIP_TRY(solid_set_attrs());
   HIP_TRY(plan_set_attrs_f64());
   HIP_TRY(plan_set_attrs_f32());
   HIP_TRY(plan_set_attrs_f64p());
@@ -164,9 +168,11 @@ eri4_status ensure_device(DeviceState** st) {
     static std::vector<double> boys;
     static std::vector<uint32_t> rt;
     static std::vector<int> rs;
+    static std::vector<double> st;
     if (boys.empty()) {
       make_boys_table(boys);
       make_rtabs(rt, rs);
+      make_solid_table(st);
     }
     if ((int)rt.size() != 2 * 2 * kRtabEntries) return fail(ERI4_ERROR_INTERNAL, "recursion table size mismatch");
     if (hipMalloc(&d.boys, boys.size() * sizeof(double)) != hipSuccess)
@@ -175,6 +181,9 @@ eri4_status ensure_device(DeviceState** st) {
       return fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation of the recursion tables failed");
     HIP_TRY(hipMemcpy(d.boys, boys.data(), boys.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.rtab, rt.data(), rt.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (hipMalloc(&d.stab, st.size() * sizeof(double)) != hipSuccess)
+      return fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation of the solid-harmonic table failed");
+    HIP_TRY(hipMemcpy(d.stab, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
     for (int i = 0; i < 2 * (kMaxL + 1); ++i) d.rstart[i] = rs[i];
     eri4_status s = set_attrs();
     if (s != ERI4_SUCCESS) return s;
@@ -239,7 +248,7 @@ bool try_params(int la, int lb, int lc, int ld, int kmax, int rb, int lay, const
   const int maxc = rb == 4 ? 2 : (slab && rb == 1 ? kMaxC1 : 4);
   if (p.lds_bytes > limit || p.L > kMaxL || (p.nqb + 7) / 8 > maxc) return false;
   if (!slab && p.L > kBoxLMax) return false;  // the box recursion holds kRPerBox entries per thread
-  p.rtab_off = d->rstart[(slab ? 1 : 0) * (kMaxL + 1) + p.L];
+  p.rtab_off = d ? d->rstart[(slab ? 1 : 0) * (kMaxL + 1) + p.L] : 0;
   *out = p;
   return true;
 }
@@ -252,6 +261,23 @@ bool pick_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d,
   for (const auto& o : order)
     if (try_params(la, lb, lc, ld, kmax, o[0], o[1], d, limit, out)) return true;
   return false;
+}
+
+// Solid-harmonic output: the library's tile for the class, with rows and
+// columns over the 2l+1 real solid harmonics of each shell; hbs / hks doubles
+// of H per bra / ket primitive pair (rows padded to whole tiles, columns to
+// whole 16-column blocks, k to the padded Hermite counts).
+bool solid_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* p, int64_t* hbs,
+                  int64_t* hks) {
+  if (!pick_params(la, lb, lc, ld, kmax, d, kMaxLdsBytes, p)) return false;
+  p->na = 2 * la + 1; p->nb = 2 * lb + 1; p->nc = 2 * lc + 1; p->nd = 2 * ld + 1;
+  p->nab = p->na * p->nb;
+  p->ncd = p->nc * p->nd;
+  p->nrt = (p->nab + 16 * p->rb - 1) / (16 * p->rb);
+  p->ncdb = (p->ncd + 15) / 16;
+  *hbs = (int64_t)p->nrt * p->rb * 16 * p->np4;
+  *hks = (int64_t)p->ncdb * 16 * p->nq4;
+  return true;
 }
 
 }  // namespace
@@ -311,6 +337,71 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets, const 
   return ERI4_SUCCESS;
 }
 
+static eri4_status check_class(int la, int lb, int lc, int ld, int64_t nquartets, int kmax) {
+  if (la < 0 || lb < 0 || lc < 0 || ld < 0)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "angular momenta must be >= 0 (got %d %d %d %d)", la, lb, lc, ld);
+  if (la > ERI4_MAX_L || lb > ERI4_MAX_L || lc > ERI4_MAX_L || ld > ERI4_MAX_L)
+    return fail(ERI4_ERROR_UNSUPPORTED, "angular momentum above %d is not supported (got %d %d %d %d)",
+                ERI4_MAX_L, la, lb, lc, ld);
+  if (nquartets < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "nquartets must be >= 0");
+  if (kmax < 1 || kmax > ERI4_MAX_K)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "kmax must be in 1..%d (got %d)", ERI4_MAX_K, kmax);
+  return ERI4_SUCCESS;
+}
+
+eri4_status eri4_solid_coefficients(int l, double* C) {
+  g_err.clear();
+  if (l < 0 || l > ERI4_MAX_L) return fail(ERI4_ERROR_INVALID_ARGUMENT, "l must be in 0..%d (got %d)", ERI4_MAX_L, l);
+  if (!C) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL output array");
+  solid_dense(l, C);
+  return ERI4_SUCCESS;
+}
+
+int64_t eri4_solid_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets) {
+  if (check_class(la, lb, lc, ld, nquartets, kmax) != ERI4_SUCCESS) return -1;
+  ClassParams p;
+  int64_t hbs, hks;
+  if (!solid_params(la, lb, lc, ld, kmax, nullptr, &p, &hbs, &hks)) return -1;
+  return nquartets * kmax * kmax * (hbs + hks);
+}
+
+eri4_status eri4_batch_solid(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                             const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                             double* work, int64_t work_size, double* out, hipStream_t stream) {
+  g_err.clear();
+  eri4_status st = check_class(la, lb, lc, ld, nquartets, kmax);
+  if (st != ERI4_SUCCESS) return st;
+  if (nquartets == 0) return ERI4_SUCCESS;
+  if (!centers || !exponents || !coeffs || !nprim || !out || !work)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  ClassParams p;
+  int64_t hbs, hks;
+  if (!solid_params(la, lb, lc, ld, kmax, nullptr, &p, &hbs, &hks))
+    return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
+  // quartets per pass: what the workspace holds (H of every primitive pair),
+  // within the grid limits
+  const int64_t perq = (int64_t)kmax * kmax * (hbs + hks);
+  int64_t chunk = work_size / perq;
+  if (chunk < 1)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below one quartet's %lld",
+                (long long)work_size, (long long)perq);
+  DeviceState* d;
+  st = ensure_device(&d);
+  if (st != ERI4_SUCCESS) return st;
+  (void)solid_params(la, lb, lc, ld, kmax, d, &p, &hbs, &hks);  // the same tile, with the device's table offsets
+  chunk = std::min<int64_t>(chunk, std::min<int64_t>(((int64_t)1 << 30) / p.nrt, INT32_MAX));
+  double* hbra = work;
+  for (int64_t q0 = 0; q0 < nquartets; q0 += chunk) {
+    const int64_t nq = std::min(chunk, nquartets - q0);
+    double* hket = hbra + nq * kmax * kmax * hbs;
+    hipError_t e = solid_h_launch(p, nq, stream, centers, exponents, coeffs, nprim, d->stab, hbra, hket, q0, hbs, hks);
+    if (e == hipSuccess)
+      e = solid_launch(p, dim3((unsigned)(nq * p.nrt)), stream, Tables{d->boys, d->rtab}, centers, exponents, coeffs,
+                       nprim, out, q0, hbra, hket, hbs, hks);
+    if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
+  }
+  return ERI4_SUCCESS;
+}
 
 // ---------------------------------------------------------------------------
 // plans: many classes and contraction lengths in one persistent launch

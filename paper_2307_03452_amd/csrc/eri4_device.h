@@ -440,6 +440,108 @@ __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double*
     }
 }
 
+// Solid-harmonic mode: the transform matrices H = (C_a x C_b) E of one
+// primitive pair come from device memory (solid_h_kernel), stored in the
+// operand order of the matrix cores: for row (or column) block u and k step s,
+// 64 doubles, lane l holding H[16u + (l & 15)][4s + (l >> 4)].  A wave's load of
+// one operand is one contiguous 512-byte read.
+
+// First transform, A operand from H: acc[r][c] += sum_p H[row block r][p] [p|q].
+// H points at this lane's element of row block 0, k step 0; operands of step
+// k+8 are requested while step k runs.
+template <int NR, int NC, bool SLAB>
+__device__ __forceinline__ void gemm1_h(typename Acc<false>::type (&acc)[NR][NC], const double* __restrict__ H,
+                                        const double* __restrict__ R, const int2* __restrict__ ptab,
+                                        const int (&offq)[NC], const int (&tq)[NC], int np4, int L, int S1,
+                                        int lane) {
+  const int g = lane >> 4;
+  const int rs = np4 * 16;  // doubles per row block
+  double a0[NR], a1[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    a0[r] = H[r * rs];
+    a1[r] = H[r * rs + min(4, np4 - 4) * 16];
+  }
+  int2 pt = ptab[g];
+  for (int kk = 0; kk < np4; kk += 4) {
+    double b[NC], a2[NR];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if constexpr (SLAB) {
+        const int t = (pt.x >> 24) + tq[c];
+        b[c] = R[slab_base(t, L, S1) + pt.y + offq[c]];
+      } else {
+        b[c] = R[pt.y + offq[c]];
+      }
+    }
+    pt = ptab[min(kk + 4, np4 - 4) + g];
+    const int k2 = min(kk + 8, np4 - 4);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a2[r] = H[r * rs + k2 * 16];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[r][c] = mfma16<false>(a0[r], b[c], acc[r][c]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      a0[r] = a1[r];
+      a1[r] = a2[r];
+    }
+  }
+}
+
+// Second transform for one group of NC output column blocks, B operand from
+// H_cd (Hk: this lane's element of column block 0, k step 0), then the output
+// write, as gemm2_group.
+template <int NR, int NC>
+__device__ __forceinline__ void gemm2_group_h(const ClassParams& cp, const double* __restrict__ X,
+                                              const double* __restrict__ Hk, int cb0, int row0,
+                                              double* __restrict__ outq, bool first, int lane) {
+  const int g = lane >> 4, n = lane & 15;
+  const int cs = cp.nq4 * 16;  // doubles per column block
+  typename Acc<false>::type acc[NR][NC];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[r][c] = acc_zero<false>();
+  const int xs = cp.xs, nq4 = cp.nq4;
+  double b0[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) b0[c] = Hk[(cb0 + 8 * c) * cs];
+  for (int kk = 0; kk < nq4; kk += 4) {
+    double a[NR], b1[NC];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a[r] = X[(r * 16 + n) * xs + kk + g];
+    const int kn = min(kk + 4, nq4 - 4);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) b1[c] = Hk[(cb0 + 8 * c) * cs + kn * 16];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r][c] = mfma16<false>(a[r], b0[c], acc[r][c]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) b0[c] = b1[c];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int cd = (cb0 + 8 * c) * 16 + n;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int ab = row0 + r * 16 + acc_row<false>(jj, g);
+        if (ab < cp.nab && cd < cp.ncd) {
+          double* o = outq + (int64_t)ab * cp.ncd + cd;
+          const double v = acc[r][c][jj];
+          if (first)
+            __builtin_nontemporal_store(v, o);
+          else
+            *o += v;
+        }
+      }
+    }
+}
+
 // LDS regions of the fused kernel (see make_params for the layout).
 struct Lds {
   double *sh, *baseM, *kpair, *bpair, *pqv, *box, *box1, *brae, *X, *kete;
@@ -480,10 +582,16 @@ __device__ __forceinline__ void ket_scale(const Lds& s, int kmax, int Ka, int Kb
 
 // Everything a workgroup does after its prologue, for NR valid row blocks and
 // NC1 first-transform column blocks of this wave.
-template <int NR, int NC1, int LAY, bool F32>
+// SOLID: rows and columns are real solid harmonics and both transforms read
+// their H matrices from hb / hk (this quartet's, hbs / hks doubles per
+// primitive pair, pair (i, j) at slot i * kmax + j); FP64 only.
+template <int NR, int NC1, int LAY, bool F32, bool SOLID = false>
 __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, const double* __restrict__ boys_tab,
                            const uint2 (&rent)[LAY == kLaySlab ? kRPerThread : kRPerBox], double* __restrict__ outq,
-                           int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane) {
+                           int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane,
+                           const double* __restrict__ hb = nullptr, const double* __restrict__ hk = nullptr,
+                           int64_t hbs = 0, int64_t hks = 0) {
+  static_assert(!(SOLID && F32), "solid-harmonic output runs FP64 transforms");
   constexpr bool SLAB = LAY == kLaySlab;
   const int kmax = cp.kmax;
   const double* A = s.sh;
@@ -497,7 +605,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
   // bra rows of this lane (A operand of the first transform)
   int rowx[NR], rowy[NR], rowz[NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
+  for (int r = 0; r < NR && !SOLID; ++r) {
     const int ab = row0 + r * 16 + (lane & 15);
     if (ab < cp.nab) {
       const int ia = ab / cp.nb, ib = ab - ia * cp.nb;
@@ -561,9 +669,10 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
           for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
           s.baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (s.bpair[1] * (s.kpair[1] * s.kpair[11])) * F;
         }
-      } else if (wave == 1) {
-        build_etab(s.brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / s.bpair[0], s.bpair + 5, s.bpair + 8, false,
-                   lane);
+      } else if constexpr (!SOLID) {
+        if (wave == 1)
+          build_etab(s.brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / s.bpair[0], s.bpair + 5, s.bpair + 8, false,
+                     lane);
       }
       __syncthreads();
       if constexpr (LAY == kLayBox2)
@@ -571,8 +680,13 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       else
         hermite_r_lds(s.box, s.baseM, cp.L, s.pqv, rent, tid);
       // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
-      if constexpr (NC1 > 0)
+      if constexpr (NC1 > 0 && SOLID) {
+        const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
+        gemm1_h<NR, NC1, SLAB>(acc1, hb + (i * kmax + j) * hbs + (row0 / 16) * (cp.np4 * 16) + lane, s.box, s.ptab,
+                               offq, tq, cp.np4, cp.L, cp.S1, lane);
+      } else if constexpr (NC1 > 0) {
         gemm1_pair<NR, NC1, SLAB, F32>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, tq, cp.np4, cp.L, cp.S1, lane);
+      }
       __syncthreads();
     }
 
@@ -588,8 +702,10 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
             s.X[(r * 16 + acc_row<F32>(jj, lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = acc1[r][c][jj];
         }
     }
-    if (wave == 0)
-      build_etab(s.kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / s.kpair[0], s.kpair + 5, s.kpair + 8, true, lane);
+    if constexpr (!SOLID) {
+      if (wave == 0)
+        build_etab(s.kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / s.kpair[0], s.kpair + 5, s.kpair + 8, true, lane);
+    }
     __syncthreads();
 
     // second transform, written to HBM (accumulated over kl); groups of
@@ -600,7 +716,16 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       const int ng = min(G2, ncbw - g0);
       const int cb0 = wave + 8 * g0;
       const bool first = kl == 0;
-      if constexpr (G2 == 4) {
+      if constexpr (SOLID) {
+        const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
+        const double* hkp = hk + (k * kmax + l) * hks + lane;
+        if (ng >= 2 && G2 >= 2)
+          gemm2_group_h<NR, 2>(cp, s.X, hkp, cb0, row0, outq, first, lane);
+        else
+          gemm2_group_h<NR, 1>(cp, s.X, hkp, cb0, row0, outq, first, lane);
+        if (ng == 3) gemm2_group_h<NR, 1>(cp, s.X, hkp, cb0 + 16, row0, outq, first, lane);
+        if (ng == 4) gemm2_group_h<NR, 2>(cp, s.X, hkp, cb0 + 16, row0, outq, first, lane);
+      } else if constexpr (G2 == 4) {
         if (ng == 4)
           gemm2_group<NR, 4, F32>(cp, s.X, s.kete, s.qtab, cb0, row0, outq, first, unscale, lane);
         else if (ng == 3)
@@ -626,7 +751,8 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
 // [q][4][3], exps/coefs [q][4][kmax]) or from a bra and a ket list of shell
 // pairs (PAIRS true: bra pair q / nket, ket pair q % nket, each list centers
 // [i][2][3], exps/coefs [i][2][kmax]; centers/exps/coefs are the bra list).
-template <int RB, int LAY, bool F32, bool PAIRS>
+// SOLID: solid-harmonic rows and columns, H matrices from hb / hk (fused_body).
+template <int RB, int LAY, bool F32, bool PAIRS, bool SOLID = false>
 __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned char* lds,
                                              const double* __restrict__ boys_tab,
                                              const uint2* __restrict__ rtab_L,
@@ -635,7 +761,9 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
                                              double* __restrict__ outq, int64_t q, int rt, int tid, int wave,
                                              int lane, const double* __restrict__ kcenters,
                                              const double* __restrict__ kexps, const double* __restrict__ kcoefs,
-                                             int64_t nket) {
+                                             int64_t nket, const double* __restrict__ hb = nullptr,
+                                             const double* __restrict__ hk = nullptr, int64_t hbs = 0,
+                                             int64_t hks = 0) {
   constexpr bool SLAB = LAY == kLaySlab;
   const int kmax = cp.kmax;
   Lds s;
@@ -697,7 +825,8 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
   }
   const int nc1 = (wave < cp.nqb) ? min(kMaxC1, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
   const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                             // valid row blocks of this tile
-#define BODY(NR, NC1) fused_body<NR, NC1, LAY, F32>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane)
+#define BODY(NR, NC1) \
+  fused_body<NR, NC1, LAY, F32, SOLID>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane, hb, hk, hbs, hks)
   constexpr int NR2 = RB >= 2 ? 2 : 1;
   if constexpr (RB == 4) {
     // 64-row tiles (kets with at most 2 column blocks per wave): the last tile
@@ -753,6 +882,29 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_fused_kernel(
   process_tile<RB, LAY, false, false>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
                                       out + q * (int64_t)cp.nab * cp.ncd, q, rt, tid, wave, lane, nullptr,
                                       nullptr, nullptr, 0);
+}
+
+// Solid-harmonic output, one class: as eri4_fused_kernel with rows and columns
+// over real solid harmonics (cp.nab = (2la+1)(2lb+1), cp.ncd = (2lc+1)(2ld+1)).
+// The H matrices of quartet q0 + i sit at hbra + i * kmax^2 * hbs and
+// hket + i * kmax^2 * hks (solid_h_kernel).
+template <int RB, int LAY>
+__global__ __launch_bounds__(kThreads, 1) void eri4_solid_kernel(
+    const ClassParams cp, const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
+    const double* __restrict__ centers, const double* __restrict__ exps,
+    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, double* __restrict__ out,
+    int64_t q0, const double* __restrict__ hbra, const double* __restrict__ hket, int64_t hbs, int64_t hks) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t i = blockIdx.x / cp.nrt;
+  const int64_t q = q0 + i;
+  const int rt = blockIdx.x % cp.nrt;
+  const int64_t kk2 = (int64_t)cp.kmax * cp.kmax;
+  process_tile<RB, LAY, false, false, true>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
+                                            out + q * (int64_t)cp.nab * cp.ncd, q, rt, tid, wave, lane, nullptr,
+                                            nullptr, nullptr, 0, hbra + i * kk2 * hbs, hket + i * kk2 * hks, hbs,
+                                            hks);
 }
 
 // Persistent kernel for a plan: work items {quartet, row tile | class << 16},
@@ -835,6 +987,15 @@ hipError_t plan_launch_t(dim3 grid, int lds_bytes, hipStream_t s, const Tables& 
   hipLaunchKernelGGL((eri4_plan_kernel<F32, PAIRS>), grid, dim3(kThreads), lds_bytes, s, a.classes, a.items,
                      a.nitems, a.qoff, a.nprim, a.counter, t.boys, t.rtab, h.centers, h.exps, h.coefs, a.out,
                      h.kcenters, h.kexps, h.kcoefs, h.nket);
+  return hipGetLastError();
+}
+
+template <int RB, int LAY>
+hipError_t solid_launch_t(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
+                          const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0,
+                          const double* hbra, const double* hket, int64_t hbs, int64_t hks) {
+  hipLaunchKernelGGL((eri4_solid_kernel<RB, LAY>), grid, dim3(kThreads), p.lds_bytes, s, p, t.boys, t.rtab, centers,
+                     exps, coefs, nprim, out, q0, hbra, hket, hbs, hks);
   return hipGetLastError();
 }
 

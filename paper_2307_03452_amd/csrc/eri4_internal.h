@@ -62,6 +62,17 @@ __host__ __device__ constexpr int r_offset(bool slab, int L, int t, int u, int v
 // t, u, v).  The first entry of each table is (0,0,0) with all fields 0.
 constexpr int kRtabEntries = 35960;  // sum_{L=0}^{28} nherm(L), per layout
 
+// Solid-harmonic coefficient table (make_solid_table): per (l, m) one entry of
+// kSolidEntry doubles, the count and up to kSolidTerms (Cartesian index,
+// coefficient) pairs; kSolidRows = 2 * kTableLMax + 1 rows per l.
+constexpr int kSolidTerms = 16;
+constexpr int kSolidEntry = 1 + 2 * kSolidTerms;
+constexpr int kSolidRows = 2 * kTableLMax + 1;
+// Hermite functions of one side (total order <= 2 * kTableLMax), padded to 4,
+// and the doubles of that side's three 1-d E tables.
+constexpr int kMaxHerm = (nherm(2 * kTableLMax) + 3) & ~3;
+constexpr int kMaxEtab = 3 * ((kTableLMax + 1) * (kTableLMax + 1) + 1) * odd_row(2 * kTableLMax + 2);
+
 // LDS of one compute unit (gfx950).
 constexpr int kMaxLdsBytes = 160 * 1024;
 

@@ -48,7 +48,8 @@ STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UN
 EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version", "eri4_init",
            "eri4_batch", "eri4_plan_create", "eri4_plan_create_tuned", "eri4_plan_output_size", "eri4_plan_output_offsets",
            "eri4_plan_execute", "eri4_plan_destroy", "eri4_plan_create_pairs", "eri4_plan_execute_pairs",
-           "eri4_boys", "eri4_hermite_r", "eri4_hermite_e")
+           "eri4_boys", "eri4_hermite_r", "eri4_hermite_e", "eri4_solid_coefficients", "eri4_solid_work_size",
+           "eri4_batch_solid")
 
 _lib = None
 
@@ -77,6 +78,12 @@ def lib() -> ctypes.CDLL:
         L.eri4_init.restype = c_int
         L.eri4_batch.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp]
         L.eri4_batch.restype = c_int
+        L.eri4_solid_coefficients.argtypes = [c_int, vp]
+        L.eri4_solid_coefficients.restype = c_int
+        L.eri4_solid_work_size.argtypes = [c_int] * 5 + [i64]
+        L.eri4_solid_work_size.restype = i64
+        L.eri4_batch_solid.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, i64, vp, vp]
+        L.eri4_batch_solid.restype = c_int
         L.eri4_plan_create.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int]
         L.eri4_plan_create.restype = c_int
         L.eri4_plan_create_tuned.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int, vp, c_int]
@@ -161,6 +168,46 @@ def batch(ls, centers, exps, coefs, nprim, out=None, stream=None):
     _check(lib().eri4_batch(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
                             _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(out, "float64"),
                             _stream(stream)))
+    return out
+
+
+def nsolid(l: int) -> int:
+    return 2 * int(l) + 1
+
+
+def solid_coefficients(l: int):
+    """The library's C[2l+1][ncart(l)] (host numpy array): coefficient of each
+    Cartesian component in each real solid harmonic, rows m = -l..l."""
+    import numpy as np
+    C = np.zeros((nsolid(l), ncart(l)))
+    _check(lib().eri4_solid_coefficients(int(l), C.ctypes.data_as(ctypes.c_void_p)))
+    return C
+
+
+def solid_work_size(ls, kmax: int, nq: int) -> int:
+    """Doubles of workspace eri4_batch_solid needs to run nq quartets in one pass."""
+    n = lib().eri4_solid_work_size(*(int(x) for x in ls), int(kmax), int(nq))
+    if n < 0:
+        raise ValueError("bad class or sizes")
+    return n
+
+
+def batch_solid(ls, centers, exps, coefs, nprim, work=None, out=None, stream=None):
+    """(ab|cd) over real solid harmonics for one class: out float64
+    [nq, 2la+1, 2lb+1, 2lc+1, 2ld+1].  work: float64 device scratch for the H
+    matrices (default: enough for one pass over all quartets)."""
+    import torch
+    la, lb, lc, ld = (int(x) for x in ls)
+    nq = centers.shape[0]
+    kmax = exps.shape[2]
+    if out is None:
+        out = torch.empty((nq, nsolid(la), nsolid(lb), nsolid(lc), nsolid(ld)), dtype=torch.float64,
+                          device=centers.device)
+    if work is None:
+        work = torch.empty(max(1, solid_work_size(ls, kmax, nq)), dtype=torch.float64, device=centers.device)
+    _check(lib().eri4_batch_solid(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
+                                  _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(work, "float64"),
+                                  work.numel(), _ptr(out, "float64"), _stream(stream)))
     return out
 
 

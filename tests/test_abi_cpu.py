@@ -197,3 +197,40 @@ def test_uneven_batch_recipe():
             zz = z[:, None] + z[None, :]
             S = inputs._dfact(2 * l - 1) / (2 * zz) ** l * (np.pi / zz) ** 1.5
             assert abs(c @ S @ c - 1.0) < 1e-12
+
+
+def test_library_solid_coefficients_match_the_oracles():
+    """The library writes its own Cartesian-to-solid table (host C++); it must
+    agree with the oracle's exact-rational one for every l."""
+    import numpy as np
+    from oracle import solid
+    for l in range(8):
+        C = eri4.solid_coefficients(l)
+        ref = solid.solid_matrix(l)
+        assert C.shape == ref.shape
+        assert np.array_equal(C != 0, ref != 0), l
+        assert np.abs(C - ref).max() <= 4e-16 * np.abs(ref).max(), l
+    L = eri4.lib()
+    assert L.eri4_solid_coefficients(8, ctypes.c_void_p(1)) == STATUS_INVALID
+    assert L.eri4_solid_coefficients(2, None) == STATUS_INVALID
+
+
+def test_solid_work_size_and_host_errors():
+    import numpy as np
+    L = eri4.lib()
+    # (ii|ii), K=1: H for one bra pair (13 x 13 = 169 rows, padded to whole tiles)
+    # and one ket pair (169 columns, padded to 16), times the padded Hermite counts
+    n1 = eri4.solid_work_size((6, 6, 6, 6), 1, 1)
+    assert n1 > 0 and eri4.solid_work_size((6, 6, 6, 6), 1, 10) == 10 * n1
+    assert eri4.solid_work_size((6, 6, 6, 6), 2, 1) == 4 * n1
+    nk = 11 * 16 * 456
+    assert (n1 - nk) % (16 * 456) == 0 and (n1 - nk) // (16 * 456) >= 11
+    assert L.eri4_solid_work_size(8, 0, 0, 0, 1, 1) == -1
+    assert L.eri4_solid_work_size(0, 0, 0, 0, 0, 1) == -1
+    assert L.eri4_solid_work_size(0, 0, 0, 0, 1, -1) == -1
+    p = ctypes.c_void_p(16)  # never dereferenced: the calls fail on the host first
+    assert L.eri4_batch_solid(2, 2, 2, 2, 4, p, p, p, p, 1, p, 1, p, None) == STATUS_INVALID
+    assert b"workspace" in L.eri4_last_error()
+    assert L.eri4_batch_solid(2, 2, 2, 2, 4, p, p, p, p, 1, None, 10 ** 9, p, None) == STATUS_INVALID
+    assert L.eri4_batch_solid(2, 2, 9, 2, 4, p, p, p, p, 1, p, 10 ** 9, p, None) == STATUS_UNSUPPORTED
+    assert L.eri4_batch_solid(2, 2, 2, 2, 0, None, None, None, None, 1, None, 0, None, None) == 0
