@@ -456,6 +456,8 @@ def main():
                     help="timed steps of the mixed-batch with FP32 transforms, compared with FP64 (0: skip)")
     ap.add_argument("--stream-steps", type=int, default=1,
                     help="run the l=7 classes and the 50k-quartet serving stream (0: skip)")
+    ap.add_argument("--solid-steps", type=int, default=3,
+                    help="timed calls of each solid-harmonic (ii|ii) batch (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -515,7 +517,8 @@ def main():
         rec["stream"] = time_stream()
         rec["low_l"] = time_low_l()
         rec["pairs"] = time_pairs()
-        rec["solid"] = time_solid()
+    if args.solid_steps > 0 and args.workload == "iiii_k1":
+        rec["solid"] = time_solid(args.solid_steps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb
