@@ -253,7 +253,7 @@ def time_pairs(nbra=128, nket=128, kmax=3, reps=3):
     {4,5,6} per shell and contraction lengths 1..3, against the quartet plan
     over the expanded batch (same quartets, per-quartet shell arrays)."""
     import torch
-    from paper_2307_03452_amd import eri4, inputs
+    from paper_2307_03452_amd import eri4, inputs, metrics
     bra, ket = inputs.pair_list(nbra, 1201, kmax=kmax), inputs.pair_list(nket, 1202, kmax=kmax)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     tiles = tuned_tiles()
@@ -266,7 +266,22 @@ def time_pairs(nbra=128, nket=128, kmax=3, reps=3):
         pp.execute(*args, out=out)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / reps
+    # the same lists over real solid harmonics: H once per list entry
+    ps = eri4.PairPlan(bra.l, bra.nprim, ket.l, ket.nprim, kmax, tiles=tiles, functions="solid")
+    work = torch.empty(max(1, ps.work_size), dtype=torch.float64, device="cuda")
+    sout = ps.execute(*args, work=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ps.execute(*args, out=sout, work=work)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / reps
     b = inputs.expand_pairs(bra, ket)
+    sflops = sum(metrics.md4_flops(*(int(x) for x in b.lq[q]), int(b.nprim[q, 0] * b.nprim[q, 1]),
+                                   int(b.nprim[q, 2] * b.nprim[q, 3]), solid=True) for q in range(b.nq))
+    solid_rec = {"value": ps.output_size / ts, "unit": "integrals/s", "ms_per_step": ts * 1e3,
+                 "pct_fp64_peak": 100 * sflops / ts / 1e12 / FP64_PEAK_TFLOPS, "workspace_bytes": ps.work_size * 8}
+    del work, sout
     _, qout, tq = time_plan(b, "fp64", reps, 1, tiles)
     flops = md4_flops_batch(b.lq, b.nprim)
     return {"workload": "bra list x ket list: %d x %d shell pairs, l in {4,5,6} per shell, K per shell 1..%d"
@@ -275,7 +290,8 @@ def time_pairs(nbra=128, nket=128, kmax=3, reps=3):
             "pct_fp64_peak": 100 * flops / t / 1e12 / FP64_PEAK_TFLOPS,
             "quartet_plan_ms_per_step": tq * 1e3, "bitwise_equal_to_quartet_plan": bool(torch.equal(out, qout)),
             "input_bytes": int(sum(a.numel() * 8 for a in args)),
-            "quartet_plan_input_bytes": int((b.centers.size + b.exps.size + b.coefs.size) * 8)}
+            "quartet_plan_input_bytes": int((b.centers.size + b.exps.size + b.coefs.size) * 8),
+            "solid": solid_rec}
 
 
 def time_solid(reps=3):

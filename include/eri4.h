@@ -205,6 +205,9 @@ eri4_status eri4_plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* 
  */
 typedef enum { ERI4_LAYOUT_BOX = 0, ERI4_LAYOUT_SLAB = 1, ERI4_LAYOUT_BOX2 = 2 } eri4_layout;
 
+/* basis functions of the output (pair-list plans) */
+typedef enum { ERI4_CARTESIAN = 0, ERI4_SOLID = 1 } eri4_functions;
+
 typedef struct {
   int32_t l[4];           /* class (la lb|lc ld) */
   int32_t kq_min, kq_max; /* range of nprim[a]*nprim[b]*nprim[c]*nprim[d] */
@@ -239,6 +242,12 @@ eri4_status eri4_plan_destroy(eri4_plan plan);
  *   ket_l, ket_nprim  int32 [nket][2]   (lc, ld) and lengths of each ket pair
  * (nbra * nket < 2^31) and otherwise behaves as eri4_plan_create_tuned
  * (choices may be NULL with nchoices 0: the library picks the tiles).
+ * functions: ERI4_CARTESIAN, or ERI4_SOLID for integrals over real solid
+ * harmonics (FP64 only; conventions as eri4_batch_solid; each quartet's block
+ * is [2la+1][2lb+1][2lc+1][2ld+1]).  A solid plan builds the H matrices of
+ * every list entry once per execute, in the caller's workspace (work, at least
+ * eri4_plan_work_size(plan) doubles, contents undefined afterwards), and every
+ * quartet of that entry reads them; Cartesian plans ignore work.
  *
  * eri4_plan_execute_pairs takes DEVICE arrays per list:
  *   bra_centers [nbra][2][3], bra_exponents / bra_coeffs [nbra][2][kmax],
@@ -250,11 +259,13 @@ eri4_status eri4_plan_destroy(eri4_plan plan);
  */
 eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t* bra_l, const int32_t* bra_nprim,
                                    int64_t nket, const int32_t* ket_l, const int32_t* ket_nprim, int kmax,
-                                   eri4_precision precision, const eri4_tile_choice* choices, int nchoices);
+                                   eri4_precision precision, eri4_functions functions,
+                                   const eri4_tile_choice* choices, int nchoices);
+int64_t eri4_plan_work_size(eri4_plan plan); /* doubles of workspace execute needs; 0 for Cartesian, -1 if NULL */
 eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, const double* bra_exponents,
                                     const double* bra_coeffs, const double* ket_centers,
-                                    const double* ket_exponents, const double* ket_coeffs, double* out,
-                                    hipStream_t stream);
+                                    const double* ket_exponents, const double* ket_coeffs, double* work,
+                                    int64_t work_size, double* out, hipStream_t stream);
 
 /*
  * Stage entry points.  They run the same device code the fused eri4_batch

@@ -149,6 +149,7 @@ std::vector<DeviceState> g_dev;
 eri4_status set_attrs() {
   HIP_TRY(fused_set_attrs());
   HIP_TRY(solid_set_attrs());
+  HIP_TRY(plan_solid_set_attrs());
   HIP_TRY(plan_set_attrs_f64());
   HIP_TRY(plan_set_attrs_f32());
   HIP_TRY(plan_set_attrs_f64p());
@@ -267,14 +268,18 @@ bool pick_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d,
 // columns over the 2l+1 real solid harmonics of each shell; hbs / hks doubles
 // of H per bra / ket primitive pair (rows padded to whole tiles, columns to
 // whole 16-column blocks, k to the padded Hermite counts).
-bool solid_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* p, int64_t* hbs,
-                  int64_t* hks) {
-  if (!pick_params(la, lb, lc, ld, kmax, d, kMaxLdsBytes, p)) return false;
-  p->na = 2 * la + 1; p->nb = 2 * lb + 1; p->nc = 2 * lc + 1; p->nd = 2 * ld + 1;
+void to_solid(ClassParams* p) {
+  p->na = 2 * p->la + 1; p->nb = 2 * p->lb + 1; p->nc = 2 * p->lc + 1; p->nd = 2 * p->ld + 1;
   p->nab = p->na * p->nb;
   p->ncd = p->nc * p->nd;
   p->nrt = (p->nab + 16 * p->rb - 1) / (16 * p->rb);
   p->ncdb = (p->ncd + 15) / 16;
+}
+
+bool solid_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* p, int64_t* hbs,
+                  int64_t* hks) {
+  if (!pick_params(la, lb, lc, ld, kmax, d, kMaxLdsBytes, p)) return false;
+  to_solid(p);
   *hbs = (int64_t)p->nrt * p->rb * 16 * p->np4;
   *hks = (int64_t)p->ncdb * 16 * p->nq4;
   return true;
@@ -418,6 +423,11 @@ struct eri4_plan_s {
   bool f32 = false;  // ERI4_PREC_FP32
   bool pairs = false;  // made from a bra and a ket list of shell pairs
   int64_t nbra = 0, nket = 0;
+  bool solid = false;  // solid-harmonic output (pair lists only)
+  int64_t work = 0;    // doubles of caller workspace for the H matrices
+  int32_t* d_pl = nullptr;   // per list entry: l of its two shells (bra entries first)
+  int32_t* d_pn = nullptr;   // per list entry: contraction lengths
+  int64_t* d_hoff = nullptr; // per list entry: where its H matrices start in the workspace
   int64_t out_size = 0;
   std::vector<int64_t> qoff;
   ClassParams* d_classes = nullptr;
@@ -434,6 +444,9 @@ static void plan_free(eri4_plan_s* p) {
   if (p->d_qoff) (void)hipFree(p->d_qoff);
   if (p->d_nprim) (void)hipFree(p->d_nprim);
   if (p->d_counter) (void)hipFree(p->d_counter);
+  if (p->d_pl) (void)hipFree(p->d_pl);
+  if (p->d_pn) (void)hipFree(p->d_pn);
+  if (p->d_hoff) (void)hipFree(p->d_hoff);
   delete p;
 }
 
@@ -449,7 +462,7 @@ static_assert(ERI4_LAYOUT_BOX == kLayBox && ERI4_LAYOUT_SLAB == kLaySlab && ERI4
 // bra and a ket list (quartet q = bra pair q / nket with ket pair q % nket).
 static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim, int kmax,
                                eri4_precision precision, const eri4_tile_choice* choices, int nchoices, bool pairs,
-                               int64_t nbra, int64_t nket) {
+                               int64_t nbra, int64_t nket, bool solid) {
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
   *plan = nullptr;
   if (precision != ERI4_PREC_FP64 && precision != ERI4_PREC_FP32)
@@ -499,6 +512,7 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
   p->pairs = pairs;
   p->nbra = nbra;
   p->nket = nket;
+  p->solid = solid;
 
   // groups of quartets with the same class and tile choice (the first matching
   // entry of the table, or none), keyed by class * (nchoices + 1) + entry + 1
@@ -542,6 +556,8 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
       return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", k[0], k[1], k[2], k[3]);
     }
   }
+  if (solid)
+    for (ClassParams& c : cps) to_solid(&c);  // rows and columns over solid functions; same tile and LDS
   p->nclasses = (int)keys.size();
   for (const ClassParams& c : cps) p->lds_bytes = std::max(p->lds_bytes, c.lds_bytes);
 
@@ -579,7 +595,8 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
 
   int ncu = 0, per_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
-  const hipError_t oe = p->pairs ? (p->f32 ? plan_occupancy_f32p(p->lds_bytes, &per_cu)
+  const hipError_t oe = p->solid ? plan_solid_occupancy(p->lds_bytes, &per_cu)
+                        : p->pairs ? (p->f32 ? plan_occupancy_f32p(p->lds_bytes, &per_cu)
                                            : plan_occupancy_f64p(p->lds_bytes, &per_cu))
                                  : (p->f32 ? plan_occupancy_f32(p->lds_bytes, &per_cu)
                                            : plan_occupancy_f64(p->lds_bytes, &per_cu));
@@ -615,7 +632,7 @@ eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int
                                    int kmax, eri4_precision precision, const eri4_tile_choice* choices,
                                    int nchoices) {
   g_err.clear();
-  return plan_create(plan, nquartets, l, nprim, kmax, precision, choices, nchoices, false, 0, 0);
+  return plan_create(plan, nquartets, l, nprim, kmax, precision, choices, nchoices, false, 0, 0, false);
 }
 
 int64_t eri4_plan_output_size(eri4_plan plan) { return plan ? plan->out_size : -1; }
@@ -629,10 +646,14 @@ eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets) {
 }
 
 // Enqueue the counter reset and the persistent kernel of a plan.
-static eri4_status plan_launch(eri4_plan plan, const Shells& shl, double* out, hipStream_t stream) {
+static eri4_status plan_launch(eri4_plan plan, const Shells& shl, double* work, int64_t work_size, double* out,
+                               hipStream_t stream) {
   if (plan->nitems == 0) return ERI4_SUCCESS;
   if (!shl.centers || !shl.exps || !shl.coefs || !out || (plan->pairs && (!shl.kcenters || !shl.kexps || !shl.kcoefs)))
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  if (plan->solid && (!work || work_size < plan->work))
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below the plan's %lld",
+                (long long)(work ? work_size : 0), (long long)plan->work);
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (dev != plan->device)
@@ -640,13 +661,18 @@ static eri4_status plan_launch(eri4_plan plan, const Shells& shl, double* out, h
   DeviceState* d;
   eri4_status st = ensure_device(&d);
   if (st != ERI4_SUCCESS) return st;
+  if (plan->solid)
+    HIP_TRY(solid_hpairs_launch((int)plan->nbra, (int)plan->nket, plan->kmax, stream, plan->d_pl, plan->d_pn, shl,
+                                plan->d_hoff, d->stab, work));
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, plan->d_counter);
   HIP_TRY(hipGetLastError());
   const PlanArgs a{plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter, shl,
                    out};
   const Tables t{d->boys, d->rtab};
   const dim3 grid(plan->grid);
-  if (plan->pairs)
+  if (plan->solid)
+    HIP_TRY(plan_solid_launch(grid, plan->lds_bytes, stream, t, a, plan->nbra, plan->d_hoff, work));
+  else if (plan->pairs)
     HIP_TRY(plan->f32 ? plan_launch_f32p(grid, plan->lds_bytes, stream, t, a)
                       : plan_launch_f64p(grid, plan->lds_bytes, stream, t, a));
   else
@@ -661,15 +687,21 @@ eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const doubl
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
   if (plan->pairs)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan made from pair lists: use eri4_plan_execute_pairs");
-  return plan_launch(plan, Shells{centers, exponents, coeffs, nullptr, nullptr, nullptr, 0}, out, stream);
+  return plan_launch(plan, Shells{centers, exponents, coeffs, nullptr, nullptr, nullptr, 0}, nullptr, 0, out, stream);
 }
 
 eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t* bra_l, const int32_t* bra_nprim,
                                    int64_t nket, const int32_t* ket_l, const int32_t* ket_nprim, int kmax,
-                                   eri4_precision precision, const eri4_tile_choice* choices, int nchoices) {
+                                   eri4_precision precision, eri4_functions functions,
+                                   const eri4_tile_choice* choices, int nchoices) {
   g_err.clear();
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
   *plan = nullptr;
+  if (functions != ERI4_CARTESIAN && functions != ERI4_SOLID)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "unknown functions %d", (int)functions);
+  const bool solid = functions == ERI4_SOLID;
+  if (solid && precision != ERI4_PREC_FP64)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "solid-harmonic output runs FP64 transforms only");
   if (nbra < 0 || nket < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "negative list length");
   if (nbra > 0 && nket > (((int64_t)1 << 31) - 1) / nbra)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "nbra * nket must be below 2^31");
@@ -686,20 +718,55 @@ eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t*
       np[4 * q] = bra_nprim[2 * i], np[4 * q + 1] = bra_nprim[2 * i + 1];
       np[4 * q + 2] = ket_nprim[2 * j], np[4 * q + 3] = ket_nprim[2 * j + 1];
     }
-  return plan_create(plan, nq, l.data(), np.data(), kmax, precision, choices, nchoices, true, nbra, nket);
+  eri4_status st = plan_create(plan, nq, l.data(), np.data(), kmax, precision, choices, nchoices, true, nbra, nket, solid);
+  if (st != ERI4_SUCCESS || !solid) return st;
+  // H matrices of every list entry, kmax^2 primitive-pair slots each
+  eri4_plan_s* p = *plan;
+  const int64_t ne = nbra + nket;
+  std::vector<int32_t> pl(2 * ne), pn(2 * ne);
+  std::vector<int64_t> hoff(ne);
+  int64_t off = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    const bool ket = e >= nbra;
+    const int64_t i = ket ? e - nbra : e;
+    const int32_t* lsrc = ket ? ket_l : bra_l;
+    const int32_t* nsrc = ket ? ket_nprim : bra_nprim;
+    pl[2 * e] = lsrc[2 * i], pl[2 * e + 1] = lsrc[2 * i + 1];
+    pn[2 * e] = nsrc[2 * i], pn[2 * e + 1] = nsrc[2 * i + 1];
+    hoff[e] = off;
+    const int l1 = pl[2 * e], l2 = pl[2 * e + 1];
+    off += (int64_t)kmax * kmax * solid_pair_units(l1, l2, ket) * 16 * ((nherm(l1 + l2) + 3) & ~3);
+  }
+  p->work = off;
+  const bool ok = hipMalloc(&p->d_pl, std::max<int64_t>(1, 2 * ne) * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(&p->d_pn, std::max<int64_t>(1, 2 * ne) * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(&p->d_hoff, std::max<int64_t>(1, ne) * sizeof(int64_t)) == hipSuccess;
+  hipError_t e = ok ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_pl, pl.data(), 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_pn, pn.data(), 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_hoff, hoff.data(), ne * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    plan_free(p);
+    *plan = nullptr;
+    return ok ? fail(ERI4_ERROR_HIP, "plan upload: %s", hipGetErrorString(e))
+              : fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation for the plan failed");
+  }
+  return ERI4_SUCCESS;
 }
+
+int64_t eri4_plan_work_size(eri4_plan plan) { return plan ? plan->work : -1; }
 
 eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, const double* bra_exponents,
                                     const double* bra_coeffs, const double* ket_centers,
-                                    const double* ket_exponents, const double* ket_coeffs, double* out,
-                                    hipStream_t stream) {
+                                    const double* ket_exponents, const double* ket_coeffs, double* work,
+                                    int64_t work_size, double* out, hipStream_t stream) {
   g_err.clear();
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
   if (!plan->pairs) return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan made from quartets: use eri4_plan_execute");
   return plan_launch(plan,
                      Shells{bra_centers, bra_exponents, bra_coeffs, ket_centers, ket_exponents, ket_coeffs,
                             plan->nket},
-                     out, stream);
+                     work, work_size, out, stream);
 }
 
 eri4_status eri4_plan_destroy(eri4_plan plan) {

@@ -73,6 +73,12 @@ constexpr int kSolidRows = 2 * kTableLMax + 1;
 constexpr int kMaxHerm = (nherm(2 * kTableLMax) + 3) & ~3;
 constexpr int kMaxEtab = 3 * ((kTableLMax + 1) * (kTableLMax + 1) + 1) * odd_row(2 * kTableLMax + 2);
 
+// Units of 16 rows (bra) or columns (ket) of the H matrices of one pair-list
+// entry: bra rows are padded to 64, a whole tile of any height.
+__host__ __device__ constexpr int solid_pair_units(int l1, int l2, bool ket) {
+  return ket ? ((2 * l1 + 1) * (2 * l2 + 1) + 15) / 16 : 4 * (((2 * l1 + 1) * (2 * l2 + 1) + 63) / 64);
+}
+
 // LDS of one compute unit (gfx950).
 constexpr int kMaxLdsBytes = 160 * 1024;
 

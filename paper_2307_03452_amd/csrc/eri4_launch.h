@@ -58,6 +58,16 @@ struct PlanArgs {
   Shells shells;
   double* out;
 };
+// Solid-harmonic pair-list plans (eri4_solid.hip): H of every bra and ket list
+// entry (pl, pn: l and contraction lengths per entry, bra entries first; hoff:
+// where each entry's H starts in h), then the persistent kernel that reads it.
+hipError_t plan_solid_set_attrs();
+hipError_t plan_solid_occupancy(int lds_bytes, int* per_cu);
+hipError_t plan_solid_launch(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a,
+                             int64_t nbra, const int64_t* hoff, const double* h);
+hipError_t solid_hpairs_launch(int nbra, int nket, int kmax, hipStream_t s, const int32_t* pl, const int32_t* pn,
+                               const Shells& x, const int64_t* hoff, const double* stab, double* h);
+
 #define ERI4_PLAN_KERNEL_ENTRIES(sfx)                                                                   \
   hipError_t plan_set_attrs_##sfx();                                                                   \
   hipError_t plan_occupancy_##sfx(int lds_bytes, int* per_cu);                                         \

@@ -26,38 +26,24 @@ namespace {
 constexpr int kHChunk = 64;
 constexpr int kSolidHLds = ncart(kTableLMax) * kHChunk * 8;
 
-__global__ __launch_bounds__(kThreads, 1) void solid_h_kernel(
-    const ClassParams cp, const double* __restrict__ centers, const double* __restrict__ exps,
-    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, const double* __restrict__ stab,
-    double* __restrict__ hbra, double* __restrict__ hket, int64_t q0, int64_t hbs, int64_t hks) {
-  extern __shared__ __align__(16) unsigned char dyn[];
-  double* P = (double*)dyn;  // [ncart(l2)][kHChunk]
+// H of primitives (z1, w1) of shell l1 and (z2, w2) of shell l2 at centres
+// c[0..2], c[3..5], into H (this pair slot's nunits units of 16 rows by nk4 k).
+// Called by all threads of a workgroup; P is LDS for kSolidHLds bytes.
+__device__ __forceinline__ void build_h(int l1, int l2, bool ket, const double* __restrict__ c, double z1, double z2,
+                                        double w1, double w2, const double* __restrict__ stab, double* __restrict__ H,
+                                        int nunits, int nk4, double* P, int tid) {
   __shared__ double tabs[kMaxEtab];
   __shared__ double pair[16];
   __shared__ int2 htab[kMaxHerm];
   __shared__ int4 terms[2][kSolidRows][kSolidTerms];  // (a_x, a_y, a_z, Cartesian index) per term
   __shared__ double tcoef[2][kSolidRows][kSolidTerms];
   __shared__ int tcount[2][kSolidRows];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int64_t iq = blockIdx.x;
-  const int64_t q = q0 + iq;
-  const int side = blockIdx.y & 1, slot = blockIdx.y >> 1;
-  const int kmax = cp.kmax;
-  const int i = slot / kmax, j = slot - (slot / kmax) * kmax;
-  const int K1 = nprim[q * 4 + 2 * side], K2 = nprim[q * 4 + 2 * side + 1];
-  if (K1 < 1 || K1 > kmax || K2 < 1 || K2 > kmax || i >= K1 || j >= K2) return;
-  const int l1 = side ? cp.lc : cp.la, l2 = side ? cp.ld : cp.lb;
+  const int lane = tid & 63;
   const int Lh = l1 + l2;
-  const int nh = nherm(Lh), nk4 = side ? cp.nq4 : cp.np4;
-  const int trow = side ? cp.tkrow : cp.tbrow, taxis = side ? cp.tkaxis : cp.tbaxis;
+  const int nh = nherm(Lh);
+  const int trow = odd_row(Lh + 2), taxis = ((l1 + 1) * (l2 + 1) + 1) * trow;
   const int s1 = 2 * l1 + 1, s2 = 2 * l2 + 1, n2c = ncart(l2);
-  const int nunits = side ? cp.ncdb : cp.nrt * cp.rb;
-  if (tid == 0) {
-    const double* c = centers + q * 12 + 6 * side;
-    const double* e = exps + (q * 4 + 2 * side) * kmax;
-    const double* w = coefs + (q * 4 + 2 * side) * kmax;
-    make_pair(pair, e[i], e[kmax + j], w[i], w[kmax + j], c, c + 3);
-  }
+  if (tid == 0) make_pair(pair, z1, z2, w1, w2, c, c + 3);
   build_htab(htab, Lh, nh, nk4, 0, 0, false, tid);
   // the two shells' solid functions as lists of (exponents, Cartesian index, coefficient)
   for (int e = tid; e < 2 * kSolidRows * kSolidTerms; e += kThreads) {
@@ -79,9 +65,8 @@ __global__ __launch_bounds__(kThreads, 1) void solid_h_kernel(
   }
   __syncthreads();
   if (tid < 64)
-    build_etab(tabs, l1, l2, trow, taxis, 0.5 / pair[0], pair + 5, pair + 8, side == 1, lane);
+    build_etab(tabs, l1, l2, trow, taxis, 0.5 / pair[0], pair + 5, pair + 8, ket, lane);
   __syncthreads();
-  double* H = side ? hket + (iq * kmax * kmax + slot) * hks : hbra + (iq * kmax * kmax + slot) * hbs;
   const int per = nk4 * 16;  // doubles per unit of 16 rows
   // element (row r, k) of H in operand order
   auto at = [&](int r, int k) { return (r >> 4) * per + (k >> 2) * 64 + (k & 3) * 16 + (r & 15); };
@@ -124,7 +109,133 @@ __global__ __launch_bounds__(kThreads, 1) void solid_h_kernel(
   }
 }
 
+// Batch form: one workgroup per (quartet q0 + blockIdx.x, side = blockIdx.y & 1,
+// pair slot blockIdx.y >> 1 = i * kmax + j); side 0 is the bra (shells a, b;
+// cp.nrt * cp.rb units, cp.np4 k), side 1 the ket (shells c, d; cp.ncdb units,
+// cp.nq4 k).  H of quartet q0 + x, slot s at hbra + (x * kmax^2 + s) * hbs (bra)
+// or hket + (x * kmax^2 + s) * hks (ket).
+__global__ __launch_bounds__(kThreads, 1) void solid_h_kernel(
+    const ClassParams cp, const double* __restrict__ centers, const double* __restrict__ exps,
+    const double* __restrict__ coefs, const int32_t* __restrict__ nprim, const double* __restrict__ stab,
+    double* __restrict__ hbra, double* __restrict__ hket, int64_t q0, int64_t hbs, int64_t hks) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  const int tid = threadIdx.x;
+  const int64_t iq = blockIdx.x;
+  const int64_t q = q0 + iq;
+  const int side = blockIdx.y & 1, slot = blockIdx.y >> 1;
+  const int kmax = cp.kmax;
+  const int i = slot / kmax, j = slot - (slot / kmax) * kmax;
+  const int K1 = nprim[q * 4 + 2 * side], K2 = nprim[q * 4 + 2 * side + 1];
+  if (K1 < 1 || K1 > kmax || K2 < 1 || K2 > kmax || i >= K1 || j >= K2) return;
+  const double* e = exps + (q * 4 + 2 * side) * kmax;
+  const double* w = coefs + (q * 4 + 2 * side) * kmax;
+  double* H = side ? hket + (iq * kmax * kmax + slot) * hks : hbra + (iq * kmax * kmax + slot) * hbs;
+  build_h(side ? cp.lc : cp.la, side ? cp.ld : cp.lb, side == 1, centers + q * 12 + 6 * side, e[i], e[kmax + j], w[i],
+          w[kmax + j], stab, H, side ? cp.ncdb : cp.nrt * cp.rb, side ? cp.nq4 : cp.np4, (double*)dyn, tid);
+}
+
+// List form: one workgroup per (list entry blockIdx.x, slot blockIdx.y = i * kmax
+// + j); entries 0..nbra-1 are the bra list, then the ket list.  An entry's H
+// starts at h + hoff[entry], kmax^2 slots of solid_pair_units(...) * 16 * nk4
+// doubles; bra rows are padded to 64 so that every tile height can read them.
+__global__ __launch_bounds__(kThreads, 1) void solid_hpairs_kernel(
+    int nbra, int kmax, const int32_t* __restrict__ pl, const int32_t* __restrict__ pn,
+    const double* __restrict__ bcenters, const double* __restrict__ bexps, const double* __restrict__ bcoefs,
+    const double* __restrict__ kcenters, const double* __restrict__ kexps, const double* __restrict__ kcoefs,
+    const int64_t* __restrict__ hoff, const double* __restrict__ stab, double* __restrict__ h) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x, slot = blockIdx.y;
+  const int i = slot / kmax, j = slot - (slot / kmax) * kmax;
+  const int K1 = pn[2 * p], K2 = pn[2 * p + 1];
+  if (K1 < 1 || K1 > kmax || K2 < 1 || K2 > kmax || i >= K1 || j >= K2) return;
+  const bool ket = p >= nbra;
+  const int64_t ip = ket ? p - nbra : p;
+  const int l1 = pl[2 * p], l2 = pl[2 * p + 1];
+  const double* e = (ket ? kexps : bexps) + ip * 2 * kmax;
+  const double* w = (ket ? kcoefs : bcoefs) + ip * 2 * kmax;
+  const int nk4 = (nherm(l1 + l2) + 3) & ~3;
+  const int nunits = solid_pair_units(l1, l2, ket);
+  build_h(l1, l2, ket, (ket ? kcenters : bcenters) + ip * 6, e[i], e[kmax + j], w[i], w[kmax + j], stab,
+          h + hoff[p] + (int64_t)slot * nunits * 16 * nk4, nunits, nk4, (double*)dyn, tid);
+}
+
+// Persistent kernel of a solid-harmonic pair-list plan: the work loop of
+// eri4_plan_kernel (shells from the bra and ket lists), both transforms reading
+// the H matrices of the quartet's bra entry (h + hoff[q / nket]) and ket entry
+// (h + hoff[nbra + q % nket]) built by solid_hpairs_kernel.
+__global__ __launch_bounds__(kThreads, 1) void eri4_plan_solid_kernel(
+    const ClassParams* __restrict__ classes, const int2* __restrict__ items, int nitems,
+    const int64_t* __restrict__ qoff, const int32_t* __restrict__ nprim, int* __restrict__ counter,
+    const double* __restrict__ boys_tab, const uint2* __restrict__ rtab, const double* __restrict__ centers,
+    const double* __restrict__ exps, const double* __restrict__ coefs, double* __restrict__ out,
+    const double* __restrict__ kcenters, const double* __restrict__ kexps, const double* __restrict__ kcoefs,
+    int64_t nket, int64_t nbra, const int64_t* __restrict__ hoff, const double* __restrict__ h) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ int next_item;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (;;) {
+    if (tid == 0) next_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(next_item);
+    __syncthreads();
+    if (it >= nitems) break;
+    const int2 w = items[it];
+    const int q = __builtin_amdgcn_readfirstlane(w.x);
+    const int rc = __builtin_amdgcn_readfirstlane(w.y);
+    const ClassParams cp = classes[rc >> 16];
+    const int rt = rc & 0xffff;
+    const uint2* rt_L = rtab + cp.rtab_off;
+    double* oq = out + qoff[q];
+    const int64_t ib = q / nket, ik = q - ib * nket;
+    const double* hb = h + hoff[ib];
+    const double* hk = h + hoff[nbra + ik];
+    const int64_t hbs = (int64_t)solid_pair_units(cp.la, cp.lb, false) * 16 * cp.np4;
+    const int64_t hks = (int64_t)cp.ncdb * 16 * cp.nq4;
+#define T(RB, LAY)                                                                                                   \
+  process_tile<RB, LAY, false, true, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, \
+                                           lane, kcenters, kexps, kcoefs, nket, hb, hk, hbs, hks)
+    const int lay = cp.lay;
+    if (lay == kLaySlab) {
+      if (cp.rb == 2) T(2, kLaySlab); else T(1, kLaySlab);
+    } else if (lay == kLayBox2) {
+      if (cp.rb == 4) T(4, kLayBox2); else if (cp.rb == 2) T(2, kLayBox2); else T(1, kLayBox2);
+    } else {
+      if (cp.rb == 4) T(4, kLayBox); else if (cp.rb == 2) T(2, kLayBox); else T(1, kLayBox);
+    }
+#undef T
+  }
+}
+
 }  // namespace
+
+hipError_t plan_solid_set_attrs() {
+  return hipFuncSetAttribute((const void*)eri4_plan_solid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             kMaxLdsBytes - 64);
+}
+
+hipError_t plan_solid_occupancy(int lds_bytes, int* per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void*)eri4_plan_solid_kernel, kThreads,
+                                                      lds_bytes);
+}
+
+hipError_t plan_solid_launch(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a,
+                             int64_t nbra, const int64_t* hoff, const double* h) {
+  const Shells& x = a.shells;
+  hipLaunchKernelGGL(eri4_plan_solid_kernel, grid, dim3(kThreads), lds_bytes, s, a.classes, a.items, a.nitems, a.qoff,
+                     a.nprim, a.counter, t.boys, t.rtab, x.centers, x.exps, x.coefs, a.out, x.kcenters, x.kexps,
+                     x.kcoefs, x.nket, nbra, hoff, h);
+  return hipGetLastError();
+}
+
+hipError_t solid_hpairs_launch(int nbra, int nket, int kmax, hipStream_t s, const int32_t* pl, const int32_t* pn,
+                               const Shells& x, const int64_t* hoff, const double* stab, double* h) {
+  const dim3 grid((unsigned)(nbra + nket), (unsigned)(kmax * kmax));
+  hipLaunchKernelGGL(solid_hpairs_kernel, grid, dim3(kThreads), kSolidHLds, s, nbra, kmax, pl, pn, x.centers, x.exps,
+                     x.coefs, x.kcenters, x.kexps, x.kcoefs, hoff, stab, h);
+  return hipGetLastError();
+}
 
 hipError_t solid_set_attrs() {
   const void* k[8] = {(const void*)eri4_solid_kernel<1, kLayBox>,  (const void*)eri4_solid_kernel<2, kLayBox>,
@@ -135,7 +246,10 @@ hipError_t solid_set_attrs() {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
     if (e != hipSuccess) return e;
   }
-  return hipFuncSetAttribute((const void*)solid_h_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kSolidHLds);
+  const hipError_t e = hipFuncSetAttribute((const void*)solid_h_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kSolidHLds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)solid_hpairs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kSolidHLds);
 }
 
 hipError_t solid_h_launch(const ClassParams& p, int64_t nq, hipStream_t s, const double* centers, const double* exps,

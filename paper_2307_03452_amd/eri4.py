@@ -19,6 +19,8 @@ ERI4_MAX_BOYS_M = 28
 
 # eri4_precision: arithmetic of the two transforms of a plan
 PRECISION = {"fp64": 0, "fp32": 1}
+# eri4_functions: basis functions of a pair-list plan's output
+FUNCTIONS = {"cartesian": 0, "solid": 1}
 # eri4_layout: where the Hermite integrals of a tile live in LDS
 LAYOUT = {"box": 0, "slab": 1, "box2": 2}
 
@@ -47,7 +49,7 @@ STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UN
 # every symbol include/eri4.h declares
 EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version", "eri4_init",
            "eri4_batch", "eri4_plan_create", "eri4_plan_create_tuned", "eri4_plan_output_size", "eri4_plan_output_offsets",
-           "eri4_plan_execute", "eri4_plan_destroy", "eri4_plan_create_pairs", "eri4_plan_execute_pairs",
+           "eri4_plan_execute", "eri4_plan_destroy", "eri4_plan_create_pairs", "eri4_plan_execute_pairs", "eri4_plan_work_size",
            "eri4_boys", "eri4_hermite_r", "eri4_hermite_e", "eri4_solid_coefficients", "eri4_solid_work_size",
            "eri4_batch_solid")
 
@@ -96,9 +98,12 @@ def lib() -> ctypes.CDLL:
         L.eri4_plan_execute.restype = c_int
         L.eri4_plan_destroy.argtypes = [vp]
         L.eri4_plan_destroy.restype = c_int
-        L.eri4_plan_create_pairs.argtypes = [ctypes.POINTER(vp), i64, vp, vp, i64, vp, vp, c_int, c_int, vp, c_int]
+        L.eri4_plan_create_pairs.argtypes = [ctypes.POINTER(vp), i64, vp, vp, i64, vp, vp, c_int, c_int, c_int, vp,
+                                             c_int]
         L.eri4_plan_create_pairs.restype = c_int
-        L.eri4_plan_execute_pairs.argtypes = [vp] * 9
+        L.eri4_plan_work_size.argtypes = [vp]
+        L.eri4_plan_work_size.restype = i64
+        L.eri4_plan_execute_pairs.argtypes = [vp] * 7 + [vp, i64, vp, vp]
         L.eri4_plan_execute_pairs.restype = c_int
         L.eri4_boys.argtypes = [c_int, i64, vp, vp, vp]
         L.eri4_boys.restype = c_int
@@ -306,9 +311,12 @@ class PairPlan(Plan):
     Quartet (i, j) is bra pair i with ket pair j, at index q = i * nket + j of
     offsets().  execute() takes the device lists: centers float64 [n, 2, 3],
     exps / coefs float64 [n, 2, kmax] for the bra and the ket side.
+    functions="solid": integrals over real solid harmonics; execute() then needs
+    a float64 device workspace of work_size doubles (allocated if not given).
     """
 
-    def __init__(self, bra_l, bra_nprim, ket_l, ket_nprim, kmax: int, precision: str = "fp64", tiles=None):
+    def __init__(self, bra_l, bra_nprim, ket_l, ket_nprim, kmax: int, precision: str = "fp64", tiles=None,
+                 functions: str = "cartesian"):
         import numpy as np
         bl, bn = (np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 2) for a in (bra_l, bra_nprim))
         kl, kn = (np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 2) for a in (ket_l, ket_nprim))
@@ -323,14 +331,22 @@ class PairPlan(Plan):
         _check(lib().eri4_plan_create_pairs(
             ctypes.byref(h), self.nbra, bl.ctypes.data_as(vp), bn.ctypes.data_as(vp), self.nket,
             kl.ctypes.data_as(vp), kn.ctypes.data_as(vp), self.kmax,
-            PRECISION[precision] if isinstance(precision, str) else int(precision),
+            PRECISION[precision] if isinstance(precision, str) else int(precision), FUNCTIONS[functions],
             ctypes.cast(arr, vp) if arr is not None else None, len(arr) if arr is not None else 0))
         self._h = h
+        self.functions = functions
 
-    def execute(self, bra_centers, bra_exps, bra_coefs, ket_centers, ket_exps, ket_coefs, out=None, stream=None):
+    @property
+    def work_size(self) -> int:
+        return lib().eri4_plan_work_size(self._h)
+
+    def execute(self, bra_centers, bra_exps, bra_coefs, ket_centers, ket_exps, ket_coefs, out=None, work=None,
+                stream=None):
         import torch
         if out is None:
             out = torch.empty(self.output_size, dtype=torch.float64, device=bra_centers.device)
+        if work is None and self.work_size > 0:
+            work = torch.empty(self.work_size, dtype=torch.float64, device=bra_centers.device)
         if out.numel() < self.output_size:
             raise ValueError("output buffer too small")
         for c, e, w, n in ((bra_centers, bra_exps, bra_coefs, self.nbra), (ket_centers, ket_exps, ket_coefs, self.nket)):
@@ -339,5 +355,5 @@ class PairPlan(Plan):
         _check(lib().eri4_plan_execute_pairs(
             self._h, _ptr(bra_centers, "float64"), _ptr(bra_exps, "float64"), _ptr(bra_coefs, "float64"),
             _ptr(ket_centers, "float64"), _ptr(ket_exps, "float64"), _ptr(ket_coefs, "float64"),
-            _ptr(out, "float64"), _stream(stream)))
+            _ptr(work, "float64"), work.numel() if work is not None else 0, _ptr(out, "float64"), _stream(stream)))
         return out

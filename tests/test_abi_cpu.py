@@ -146,9 +146,9 @@ def test_plan_create_pairs_rejects_bad_host_arrays_before_touching_a_device():
     kl, kn = np.full((2, 2), 5, np.int32), np.ones((2, 2), np.int32)
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
 
-    def create(nbra=3, bl=bl, bn=bn, nket=2, kl=kl, kn=kn, kmax=1, prec=0, plan=True):
+    def create(nbra=3, bl=bl, bn=bn, nket=2, kl=kl, kn=kn, kmax=1, prec=0, plan=True, fn=0):
         return L.eri4_plan_create_pairs(ctypes.byref(h) if plan else None, nbra, ptr(bl) if bl is not None else None,
-                                        ptr(bn), nket, ptr(kl) if kl is not None else None, ptr(kn), kmax, prec,
+                                        ptr(bn), nket, ptr(kl) if kl is not None else None, ptr(kn), kmax, prec, fn,
                                         None, 0)
 
     assert create(plan=False) == STATUS_INVALID
@@ -161,8 +161,11 @@ def test_plan_create_pairs_rejects_bad_host_arrays_before_touching_a_device():
     badn = bn.copy(); badn[2, 1] = 3
     assert create(bn=badn, kmax=2) == STATUS_INVALID and b"contraction length" in L.eri4_last_error()
     assert create(prec=5) == STATUS_INVALID and b"precision" in L.eri4_last_error()
+    assert create(fn=2) == STATUS_INVALID and b"functions" in L.eri4_last_error()
+    assert create(fn=1, prec=1) == STATUS_INVALID and b"FP64" in L.eri4_last_error()
     assert h.value is None
-    assert L.eri4_plan_execute_pairs(None, None, None, None, None, None, None, None, None) == STATUS_INVALID
+    assert L.eri4_plan_execute_pairs(None, None, None, None, None, None, None, None, 0, None, None) == STATUS_INVALID
+    assert L.eri4_plan_work_size(None) == -1
 
 
 def test_pair_list_expansion_is_bra_major():

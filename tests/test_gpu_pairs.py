@@ -100,7 +100,7 @@ def test_pair_and_quartet_plans_refuse_each_others_execute(torch):
     p = lambda t: t.data_ptr()
     assert L.eri4_plan_execute(pp._h, p(C), p(E), p(Co), p(out), None) == 1
     assert b"pair lists" in L.eri4_last_error()
-    assert L.eri4_plan_execute_pairs(qp._h, p(C), p(E), p(Co), p(C), p(E), p(Co), p(out), None) == 1
+    assert L.eri4_plan_execute_pairs(qp._h, p(C), p(E), p(Co), p(C), p(E), p(Co), None, 0, p(out), None) == 1
     assert b"quartets" in L.eri4_last_error()
 
 
@@ -113,3 +113,45 @@ def test_empty_pair_lists(torch):
         p.execute(z(nb, 3), z(nb, 1), z(nb, 1), z(nk, 3), z(nk, 1), z(nk, 1),
                   out=torch.zeros(1, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
+
+
+def test_solid_pair_plan_matches_batch_solid_and_oracle(torch):
+    """Solid-harmonic pair-list plan: every quartet equals eri4_batch_solid on
+    that quartet alone (H built per list entry instead of per quartet; the same
+    arithmetic), and sampled quartets match the oracle to the transform's bound."""
+    from oracle import solid
+    bra = inputs.pair_list(4, 51, lvals=(2, 4, 5), kmax=2)
+    ket = inputs.pair_list(5, 52, lvals=(3, 4, 6), kmax=2)
+    p = eri4.PairPlan(bra.l, bra.nprim, ket.l, ket.nprim, 2, functions="solid")
+    assert p.work_size > 0
+    g = p.execute(*lists(torch, bra), *lists(torch, ket))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    b = inputs.expand_pairs(bra, ket)
+    off = p.offsets()
+    sizes = [int(np.prod([2 * x + 1 for x in b.lq[q]])) for q in range(b.nq)]
+    assert off[0] == 0 and np.array_equal(off[1:], np.cumsum(sizes)[:-1]) and p.output_size == sum(sizes)
+    for q in range(b.nq):
+        ls = tuple(int(x) for x in b.lq[q])
+        s = inputs.subset(b, [q])
+        one = eri4.batch_solid(ls, dev(torch, s.centers), dev(torch, s.exps), dev(torch, s.coefs),
+                               dev(torch, s.nprim)).cpu().numpy()[0]
+        assert np.array_equal(g[off[q]:off[q] + one.size].reshape(one.shape), one), q
+    for q in (0, 7, b.nq - 1):
+        ls = tuple(int(x) for x in b.lq[q])
+        s = inputs.subset(b, [q])
+        cart = oracle.eri_md4(ls, s.centers, s.exps, s.coefs, s.nprim)
+        ref = solid.cart_to_solid(cart, ls)[0]
+        bound = solid.cart_to_solid(np.abs(cart), ls, absolute=True)[0].max()
+        got = g[off[q]:off[q] + ref.size].reshape(ref.shape)
+        assert np.abs(got - ref).max() <= TOL * bound, q
+
+
+def test_solid_pair_plan_rejects_a_small_workspace(torch):
+    bra, ket = inputs.pair_list(2, 53, kmax=1), inputs.pair_list(2, 54, kmax=1)
+    p = eri4.PairPlan(bra.l, bra.nprim, ket.l, ket.nprim, 1, functions="solid")
+    small = torch.empty(p.work_size - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(eri4.Eri4Error, match="workspace"):
+        p.execute(*lists(torch, bra), *lists(torch, ket), work=small)
+    cart = eri4.PairPlan(bra.l, bra.nprim, ket.l, ket.nprim, 1)
+    assert cart.work_size == 0
