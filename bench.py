@@ -332,6 +332,51 @@ def time_solid(reps=3):
     return out
 
 
+def time_gggg(graph_calls=100, reps=5):
+    """(gg|gg) K=1, 64 quartets (2.9e7 MD4 FLOPs each; 24 us at FP64 peak, so
+    launch overhead matters): one eri4_batch call timed with HIP events on its
+    stream, and a HIP graph of 100 calls replayed (time per call)."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs, metrics
+    wl = WORKLOADS["gggg_k1"]
+    b = make_batch(wl)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    C, E, Co, N = d(b.centers), d(b.exps), d(b.coefs), d(b.nprim)
+    out = eri4.batch(b.ls, C, E, Co, N)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    single = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        eri4.batch(b.ls, C, E, Co, N, out=out, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        single.append(e0.elapsed_time(e1))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(graph_calls):
+            eri4.batch(b.ls, C, E, Co, N, out=out, stream=s)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        with torch.cuda.stream(s):
+            g.replay()
+    e1.record(s)
+    torch.cuda.synchronize()
+    per_call = e0.elapsed_time(e1) / (reps * graph_calls)
+    flops = b.nq * metrics.md4_flops(4, 4, 4, 4, 1, 1)
+    ints = b.nq * metrics.integrals_per_quartet(4, 4, 4, 4)
+    t1 = sorted(single)[len(single) // 2]
+    return {"workload": wl["desc"], "single_launch_ms": t1, "single_pct_fp64_peak": 100 * flops / t1 / 1e9 / FP64_PEAK_TFLOPS,
+            "graph_calls": graph_calls, "graph_ms_per_call": per_call,
+            "graph_pct_fp64_peak": 100 * flops / per_call / 1e9 / FP64_PEAK_TFLOPS,
+            "value": ints / (per_call / 1e3), "unit": "integrals/s"}
+
+
 def time_stream(nq=50000, seed=1006, chunk=1024, ring=4):
     """Serving-style stream: 50 000 quartets over the 256 classes in {4..7}^4
     (Zipf counts, K=3 per shell) in chunks of 1024, each chunk a HIP graph
@@ -533,6 +578,7 @@ def main():
         rec["stream"] = time_stream()
         rec["low_l"] = time_low_l()
         rec["pairs"] = time_pairs()
+        rec["gggg_k1"] = time_gggg()
     if args.solid_steps > 0 and args.workload == "iiii_k1":
         rec["solid"] = time_solid(args.solid_steps)
     if not args.no_cpu_baseline:
