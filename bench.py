@@ -377,6 +377,45 @@ def time_gggg(graph_calls=100, reps=5):
             "value": ints / (per_call / 1e3), "unit": "integrals/s"}
 
 
+def time_coulomb(reps=3):
+    """Coulomb contraction without forming (ab|cd) (eri4_batch_coulomb): (ii|ii)
+    K=1 on the 512-quartet batch and K=5 per shell on its first 128 quartets.
+    FLOPs: the first transform 2 Nab (Kb Np)(Kk Nq), the contraction with the
+    Hermite-space density 2 Nab Kk Nq, and that density 2 Kk Nq Ncd."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs, metrics
+    import oracle
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = []
+    for K, nq in ((1, 512), (5, 128)):
+        b = inputs.subset(inputs.iiii(K=K), range(nq))
+        D = inputs.ket_densities(b, seed=1300 + K)
+        C, E, Co, N, Dd = d(b.centers), d(b.exps), d(b.coefs), d(b.nprim), d(D)
+        work = torch.empty(eri4.coulomb_work_size(b.ls, b.kmax, nq), dtype=torch.float64, device="cuda")
+        o = eri4.batch_coulomb(b.ls, C, E, Co, N, Dd, work=work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eri4.batch_coulomb(b.ls, C, E, Co, N, Dd, work=work, out=o)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        kb = K * K
+        npp = metrics.nherm(12)
+        flops = nq * (2 * 784 * (kb * npp) * (kb * npp) + 2 * 784 * kb * npp + 2 * kb * npp * 784)
+        I = oracle.eri_md4(b.ls, b.centers[:2], b.exps[:2], b.coefs[:2], b.nprim[:2])
+        ref = np.einsum("qabcd,qcd->qab", I, D[:2])
+        bound = np.einsum("qabcd,qcd->qab", np.abs(I), np.abs(D[:2]))
+        g = o[:2].cpu().numpy()
+        err = max(float(np.abs(g[i] - ref[i]).max() / bound[i].max()) for i in range(2))
+        out.append({"workload": "(ii|ii) Coulomb contraction J_ab = sum_cd (ab|cd) D_cd, K=%d per shell, %d quartets"
+                                % (K, nq), "ms_per_step": t * 1e3,
+                    "pct_fp64_peak": 100 * flops / t / 1e12 / FP64_PEAK_TFLOPS,
+                    "output_bytes": nq * 784 * 8, "integrals_contracted_per_s": nq * 784 * 784 / t,
+                    "parity_max_err_2q_rel_contraction_bound": err})
+        del work, o
+    return out
+
+
 def time_stream(nq=50000, seed=1006, chunk=1024, ring=4):
     """Serving-style stream: 50 000 quartets over the 256 classes in {4..7}^4
     (Zipf counts, K=3 per shell) in chunks of 1024, each chunk a HIP graph
@@ -581,6 +620,7 @@ def main():
         rec["gggg_k1"] = time_gggg()
     if args.solid_steps > 0 and args.workload == "iiii_k1":
         rec["solid"] = time_solid(args.solid_steps)
+        rec["coulomb"] = time_coulomb(args.solid_steps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

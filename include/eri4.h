@@ -149,6 +149,28 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets,
  * INVALID_ARGUMENT.  FP64 throughout; enqueue-only (nothing is allocated
  * after the first call on a device).
  */
+/*
+ * Coulomb contraction without forming (ab|cd): for every quartet,
+ *   J_ab = sum_cd (ab|cd) D_cd
+ * with D the quartet's own ket density block.  The paper names computing Fock
+ * matrix elements directly from [q|ab) as the way around the transposes between
+ * its transforms (Sec. 3).  Here the ket density is taken to Hermite space per
+ * ket primitive pair, dket_q = sum_cd E_cd^q D_cd (sign of eq. (pq) included),
+ * and contracted with [ab|q] from the first transform; the second transform and
+ * the N_ab N_cd output are never formed.  FP64, Cartesian functions.
+ *   dens  device double [nquartets][Nc][Nd]   (the caller gathers each quartet's block)
+ *   out   device double [nquartets][Na][Nb]   J contributions, quartets in input order
+ *   work  device double [work_size], caller-owned scratch for dket
+ * Other arguments as eri4_batch; quartets run in passes of as many as the
+ * workspace holds (eri4_coulomb_work_size(la, lb, lc, ld, kmax, n) doubles for
+ * n quartets, -1 for bad arguments).  Symmetry (the (cd|ab) contribution, or
+ * exchange) is the caller's: each call contracts the ket index pair only.
+ */
+int64_t eri4_coulomb_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets);
+eri4_status eri4_batch_coulomb(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                               const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                               const double* dens, double* work, int64_t work_size, double* out, hipStream_t stream);
+
 eri4_status eri4_solid_coefficients(int l, double* C);
 int64_t eri4_solid_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets);
 eri4_status eri4_batch_solid(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,

@@ -150,6 +150,7 @@ eri4_status set_attrs() {
   HIP_TRY(fused_set_attrs());
   HIP_TRY(solid_set_attrs());
   HIP_TRY(plan_solid_set_attrs());
+  HIP_TRY(coulomb_set_attrs());
   HIP_TRY(plan_set_attrs_f64());
   HIP_TRY(plan_set_attrs_f32());
   HIP_TRY(plan_set_attrs_f64p());
@@ -403,6 +404,56 @@ eri4_status eri4_batch_solid(int la, int lb, int lc, int ld, int64_t nquartets, 
     if (e == hipSuccess)
       e = solid_launch(p, dim3((unsigned)(nq * p.nrt)), stream, Tables{d->boys, d->rtab}, centers, exponents, coeffs,
                        nprim, out, q0, hbra, hket, hbs, hks);
+    if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
+  }
+  return ERI4_SUCCESS;
+}
+
+// The Coulomb kernels hold kCoulLds doubles of static LDS beside the dynamic area.
+static bool coulomb_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* p,
+                           int64_t* ds) {
+  if (!pick_params(la, lb, lc, ld, kmax, d, kMaxLdsBytes - kCoulLds * 8 - 512, p)) return false;
+  *ds = 16 * (int64_t)p->nqb;
+  return true;
+}
+
+int64_t eri4_coulomb_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets) {
+  if (check_class(la, lb, lc, ld, nquartets, kmax) != ERI4_SUCCESS) return -1;
+  ClassParams p;
+  int64_t ds;
+  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds)) return -1;
+  return nquartets * kmax * kmax * ds;
+}
+
+eri4_status eri4_batch_coulomb(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                               const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                               const double* dens, double* work, int64_t work_size, double* out, hipStream_t stream) {
+  g_err.clear();
+  eri4_status st = check_class(la, lb, lc, ld, nquartets, kmax);
+  if (st != ERI4_SUCCESS) return st;
+  if (nquartets == 0) return ERI4_SUCCESS;
+  if (!centers || !exponents || !coeffs || !nprim || !dens || !out || !work)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  ClassParams p;
+  int64_t ds;
+  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds))
+    return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
+  const int64_t perq = (int64_t)kmax * kmax * ds;
+  int64_t chunk = work_size / perq;
+  if (chunk < 1)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below one quartet's %lld",
+                (long long)work_size, (long long)perq);
+  DeviceState* d;
+  st = ensure_device(&d);
+  if (st != ERI4_SUCCESS) return st;
+  (void)coulomb_params(la, lb, lc, ld, kmax, d, &p, &ds);
+  chunk = std::min<int64_t>(chunk, std::min<int64_t>(((int64_t)1 << 30) / p.nrt, INT32_MAX));
+  for (int64_t q0 = 0; q0 < nquartets; q0 += chunk) {
+    const int64_t nq = std::min(chunk, nquartets - q0);
+    hipError_t e = coulomb_dket_launch(p, nq, stream, centers, exponents, coeffs, nprim, dens, work, q0, ds);
+    if (e == hipSuccess)
+      e = coulomb_launch(p, dim3((unsigned)(nq * p.nrt)), stream, Tables{d->boys, d->rtab}, centers, exponents,
+                         coeffs, nprim, out, q0, work, ds);
     if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
   }
   return ERI4_SUCCESS;

@@ -585,13 +585,23 @@ __device__ __forceinline__ void ket_scale(const Lds& s, int kmax, int Ka, int Kb
 // SOLID: rows and columns are real solid harmonics and both transforms read
 // their H matrices from hb / hk (this quartet's, hbs / hks doubles per
 // primitive pair, pair (i, j) at slot i * kmax + j); FP64 only.
-template <int NR, int NC1, int LAY, bool F32, bool SOLID = false>
+// COUL: no second transform; the first transform's [ab|q] is contracted with
+// the ket density in Hermite space, dket[q] = sum_cd E_cd^q D_cd of ket pair
+// (k, l) at hk + (k * kmax + l) * hks (coulomb_dket_kernel), giving
+// J_ab = sum_cd (ab|cd) D_cd, written to outq[ab] (FP64, Cartesian).
+template <int NR, int NC1, int LAY, bool F32, bool SOLID = false, bool COUL = false>
 __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, const double* __restrict__ boys_tab,
                            const uint2 (&rent)[LAY == kLaySlab ? kRPerThread : kRPerBox], double* __restrict__ outq,
                            int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane,
                            const double* __restrict__ hb = nullptr, const double* __restrict__ hk = nullptr,
-                           int64_t hbs = 0, int64_t hks = 0) {
+                           int64_t hbs = 0, int64_t hks = 0, double* jt = nullptr) {
   static_assert(!(SOLID && F32), "solid-harmonic output runs FP64 transforms");
+  static_assert(!(COUL && (F32 || SOLID)), "the Coulomb contraction runs FP64 Cartesian transforms");
+  if constexpr (COUL) {
+    // J rows of the tile in jt[0..63], each wave's partial rows in
+    // jt[64 + 64 * wave ..] (kCoulLds doubles of the kernel's LDS)
+    if (tid < 64) jt[tid] = 0.0;
+  }
   constexpr bool SLAB = LAY == kLaySlab;
   const int kmax = cp.kmax;
   const double* A = s.sh;
@@ -690,6 +700,44 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       __syncthreads();
     }
 
+    if constexpr (COUL) {
+      // J rows += sum over this wave's columns q of [ab|q] dket[q]; the 16
+      // lanes of a row group hold 16 columns: reduce them, then add the waves'
+      // partial rows in a fixed order (reproducible to the bit)
+      const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
+      const double* dk = hk + (k * kmax + l) * hks;
+      double part[NR][4];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) part[r][jj] = 0.0;
+#pragma unroll
+      for (int c = 0; c < NC1; ++c) {
+        const double dv = dk[(wave + 8 * c) * 16 + (lane & 15)];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) part[r][jj] += acc1[r][c][jj] * dv;
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          double v = part[r][jj];
+#pragma unroll
+          for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+          if ((lane & 15) == 0) jt[64 + 64 * wave + r * 16 + acc_row<false>(jj, lane >> 4)] = v;
+        }
+      __syncthreads();
+      if (tid < NR * 16) {
+        double a = jt[tid];
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) a += jt[64 + 64 * w + tid];
+        jt[tid] = a;
+      }
+      __syncthreads();
+      continue;
+    }
     // [ab_tile|q] -> LDS (aliases the R box); ket tables for kl
     if constexpr (NC1 > 0) {
 #pragma unroll
@@ -743,6 +791,10 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
     }
     __syncthreads();
   }
+  if constexpr (COUL) {
+    __syncthreads();
+    if (tid < NR * 16 && row0 + tid < cp.nab) outq[row0 + tid] = jt[tid];
+  }
 }
 
 // All the work of one tile: quartet q, bra rows rt*RB*16.., whose integrals
@@ -752,7 +804,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
 // pairs (PAIRS true: bra pair q / nket, ket pair q % nket, each list centers
 // [i][2][3], exps/coefs [i][2][kmax]; centers/exps/coefs are the bra list).
 // SOLID: solid-harmonic rows and columns, H matrices from hb / hk (fused_body).
-template <int RB, int LAY, bool F32, bool PAIRS, bool SOLID = false>
+template <int RB, int LAY, bool F32, bool PAIRS, bool SOLID = false, bool COUL = false>
 __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned char* lds,
                                              const double* __restrict__ boys_tab,
                                              const uint2* __restrict__ rtab_L,
@@ -763,7 +815,7 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
                                              const double* __restrict__ kexps, const double* __restrict__ kcoefs,
                                              int64_t nket, const double* __restrict__ hb = nullptr,
                                              const double* __restrict__ hk = nullptr, int64_t hbs = 0,
-                                             int64_t hks = 0) {
+                                             int64_t hks = 0, double* jt = nullptr) {
   constexpr bool SLAB = LAY == kLaySlab;
   const int kmax = cp.kmax;
   Lds s;
@@ -818,15 +870,17 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
   const int row0 = rt * RB * 16;
   if (Ka < 1 || Ka > kmax || Kb < 1 || Kb > kmax || Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax) {
     const int nrows = min(RB * 16, cp.nab - row0);
-    double* o = outq + (int64_t)row0 * cp.ncd;
-    for (int i = tid; i < nrows * cp.ncd; i += kThreads) o[i] = __builtin_nan("");
+    const int ncols = COUL ? 1 : cp.ncd;
+    double* o = outq + (int64_t)row0 * ncols;
+    for (int i = tid; i < nrows * ncols; i += kThreads) o[i] = __builtin_nan("");
     __syncthreads();
     return;
   }
   const int nc1 = (wave < cp.nqb) ? min(kMaxC1, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
   const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                             // valid row blocks of this tile
 #define BODY(NR, NC1) \
-  fused_body<NR, NC1, LAY, F32, SOLID>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane, hb, hk, hbs, hks)
+  fused_body<NR, NC1, LAY, F32, SOLID, COUL>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane, hb, hk, \
+                                             hbs, hks, jt)
   constexpr int NR2 = RB >= 2 ? 2 : 1;
   if constexpr (RB == 4) {
     // 64-row tiles (kets with at most 2 column blocks per wave): the last tile

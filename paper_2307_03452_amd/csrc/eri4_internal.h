@@ -79,6 +79,10 @@ __host__ __device__ constexpr int solid_pair_units(int l1, int l2, bool ket) {
   return ket ? ((2 * l1 + 1) * (2 * l2 + 1) + 15) / 16 : 4 * (((2 * l1 + 1) * (2 * l2 + 1) + 63) / 64);
 }
 
+// Static LDS of the Coulomb kernels: J rows of a tile plus one partial row set
+// per wave (doubles).
+constexpr int kCoulLds = 64 + 8 * 64;
+
 // LDS of one compute unit (gfx950).
 constexpr int kMaxLdsBytes = 160 * 1024;
 

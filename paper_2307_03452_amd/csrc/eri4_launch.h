@@ -1,6 +1,6 @@
 // eri4_launch.h -- host-side entry points to the kernels of liberi4 that are
-// compiled in their own translation units (eri4_fused.hip, eri4_solid.hip and
-// the four eri4_plan*.hip).  Not part of the public ABI.
+// compiled in their own translation units (eri4_fused.hip, eri4_solid.hip,
+// eri4_coulomb.hip and the four eri4_plan*.hip).  Not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,6 +31,17 @@ hipError_t solid_h_launch(const ClassParams& p, int64_t nq, hipStream_t s, const
 hipError_t solid_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
                         const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0,
                         const double* hbra, const double* hket, int64_t hbs, int64_t hks);
+
+// Coulomb contraction (eri4_coulomb.hip): dket of every ket primitive pair of
+// quartets q0..q0+nq-1 (ds doubles each, kmax^2 slots per quartet), then the
+// integral kernels that contract [ab|q] with it.
+hipError_t coulomb_set_attrs();
+hipError_t coulomb_dket_launch(const ClassParams& p, int64_t nq, hipStream_t s, const double* centers,
+                               const double* exps, const double* coefs, const int32_t* nprim, const double* dens,
+                               double* dket, int64_t q0, int64_t ds);
+hipError_t coulomb_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
+                          const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0,
+                          const double* dket, int64_t ds);
 
 // Where the shells of quartet q come from: per-quartet arrays (nket == 0:
 // centers [q][4][3], exps/coefs [q][4][kmax]), or a bra and a ket list of

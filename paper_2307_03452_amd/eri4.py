@@ -51,7 +51,7 @@ EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version",
            "eri4_batch", "eri4_plan_create", "eri4_plan_create_tuned", "eri4_plan_output_size", "eri4_plan_output_offsets",
            "eri4_plan_execute", "eri4_plan_destroy", "eri4_plan_create_pairs", "eri4_plan_execute_pairs", "eri4_plan_work_size",
            "eri4_boys", "eri4_hermite_r", "eri4_hermite_e", "eri4_solid_coefficients", "eri4_solid_work_size",
-           "eri4_batch_solid")
+           "eri4_batch_solid", "eri4_coulomb_work_size", "eri4_batch_coulomb")
 
 _lib = None
 
@@ -86,6 +86,10 @@ def lib() -> ctypes.CDLL:
         L.eri4_solid_work_size.restype = i64
         L.eri4_batch_solid.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, i64, vp, vp]
         L.eri4_batch_solid.restype = c_int
+        L.eri4_coulomb_work_size.argtypes = [c_int] * 5 + [i64]
+        L.eri4_coulomb_work_size.restype = i64
+        L.eri4_batch_coulomb.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp, i64, vp, vp]
+        L.eri4_batch_coulomb.restype = c_int
         L.eri4_plan_create.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int]
         L.eri4_plan_create.restype = c_int
         L.eri4_plan_create_tuned.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int, vp, c_int]
@@ -213,6 +217,32 @@ def batch_solid(ls, centers, exps, coefs, nprim, work=None, out=None, stream=Non
     _check(lib().eri4_batch_solid(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
                                   _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(work, "float64"),
                                   work.numel(), _ptr(out, "float64"), _stream(stream)))
+    return out
+
+
+def coulomb_work_size(ls, kmax: int, nq: int) -> int:
+    """Doubles of workspace eri4_batch_coulomb needs to run nq quartets in one pass."""
+    n = lib().eri4_coulomb_work_size(*(int(x) for x in ls), int(kmax), int(nq))
+    if n < 0:
+        raise ValueError("bad class or sizes")
+    return n
+
+
+def batch_coulomb(ls, centers, exps, coefs, nprim, dens, work=None, out=None, stream=None):
+    """J_ab = sum_cd (ab|cd) D_cd for every quartet of one class, without
+    forming (ab|cd): dens float64 [nq, Nc, Nd] (device), returns float64
+    [nq, Na, Nb]."""
+    import torch
+    la, lb, lc, ld = (int(x) for x in ls)
+    nq = centers.shape[0]
+    kmax = exps.shape[2]
+    if out is None:
+        out = torch.empty((nq, ncart(la), ncart(lb)), dtype=torch.float64, device=centers.device)
+    if work is None:
+        work = torch.empty(max(1, coulomb_work_size(ls, kmax, nq)), dtype=torch.float64, device=centers.device)
+    _check(lib().eri4_batch_coulomb(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
+                                    _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(dens, "float64"),
+                                    _ptr(work, "float64"), work.numel(), _ptr(out, "float64"), _stream(stream)))
     return out
 
 

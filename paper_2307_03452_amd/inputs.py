@@ -242,3 +242,11 @@ def expand_pairs(bra: PairList, ket: PairList) -> Batch:
     cat = lambda x, y: np.concatenate([np.repeat(x, nk, axis=0), np.tile(y, (nb,) + (1,) * (y.ndim - 1))], axis=1)
     return Batch(None, cat(bra.centers, ket.centers), cat(bra.exps, ket.exps), cat(bra.coefs, ket.coefs),
                  cat(bra.nprim, ket.nprim).astype(np.int32), cat(bra.l, ket.l).astype(np.int32))
+
+
+def ket_densities(b: Batch, seed: int, ls=None) -> np.ndarray:
+    """A density block D[q][Nc][Nd] per quartet (uniform in [-1, 1]) for the
+    Coulomb contraction; ls defaults to the batch's class."""
+    ls = b.ls if ls is None else ls
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-1.0, 1.0, size=(b.nq, ncart(ls[2]), ncart(ls[3])))

@@ -237,3 +237,16 @@ def test_solid_work_size_and_host_errors():
     assert L.eri4_batch_solid(2, 2, 2, 2, 4, p, p, p, p, 1, None, 10 ** 9, p, None) == STATUS_INVALID
     assert L.eri4_batch_solid(2, 2, 9, 2, 4, p, p, p, p, 1, p, 10 ** 9, p, None) == STATUS_UNSUPPORTED
     assert L.eri4_batch_solid(2, 2, 2, 2, 0, None, None, None, None, 1, None, 0, None, None) == 0
+
+
+def test_coulomb_work_size_and_host_errors():
+    L = eri4.lib()
+    n1 = eri4.coulomb_work_size((6, 6, 6, 6), 1, 1)
+    assert n1 == 16 * 29  # 455 ket Hermite functions in 29 column blocks of 16
+    assert eri4.coulomb_work_size((6, 6, 6, 6), 3, 2) == 2 * 9 * n1
+    assert L.eri4_coulomb_work_size(0, 0, 0, 8, 1, 1) == -1
+    p = ctypes.c_void_p(16)  # never dereferenced: the calls fail on the host first
+    assert L.eri4_batch_coulomb(2, 2, 2, 2, 4, p, p, p, p, 1, p, p, 1, p, None) == STATUS_INVALID
+    assert b"workspace" in L.eri4_last_error()
+    assert L.eri4_batch_coulomb(2, 2, 2, 2, 4, p, p, p, p, 1, None, p, 10 ** 6, p, None) == STATUS_INVALID
+    assert L.eri4_batch_coulomb(2, 2, 2, 2, 0, None, None, None, None, 1, None, None, 0, None, None) == 0

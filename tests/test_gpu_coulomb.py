@@ -1,0 +1,92 @@
+"""Coulomb contraction without forming (ab|cd) (eri4_batch_coulomb) against the
+oracle: its Cartesian integrals contracted with the density, J_ab = sum_cd
+(ab|cd) D_cd.  Tolerance: 1e-12 times the quartet's largest
+sum_cd |(ab|cd)| |D_cd|, the scale the contraction rounds at."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03452_amd import eri4, inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    eri4.init()
+    return _t
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run(torch, b, D, work=None):
+    out = eri4.batch_coulomb(b.ls, dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs),
+                             dev(torch, b.nprim), dev(torch, D), work=work)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check(g, I, D):
+    ref = np.einsum("qabcd,qcd->qab", I, D)
+    bound = np.einsum("qabcd,qcd->qab", np.abs(I), np.abs(D))
+    assert g.shape == ref.shape
+    for q in range(ref.shape[0]):
+        scale = max(bound[q].max(), 1e-250)
+        assert np.isfinite(g[q]).all(), q
+        assert np.abs(g[q] - ref[q]).max() <= TOL * scale, (q, np.abs(g[q] - ref[q]).max() / scale)
+
+
+@pytest.mark.parametrize("ls,K,nq", [((0, 0, 0, 0), 2, 5), ((1, 0, 2, 1), (1, 3), 6), ((2, 2, 2, 2), 2, 4),
+                                     ((3, 1, 2, 3), 1, 4), ((4, 4, 4, 4), 1, 3), ((5, 4, 6, 3), 2, 2),
+                                     ((6, 6, 6, 6), 1, 2), ((6, 6, 6, 6), 2, 1), ((7, 7, 7, 7), 1, 1),
+                                     ((6, 7, 6, 7), 1, 1)])
+def test_against_oracle(torch, ls, K, nq):
+    b = inputs.class_batch(ls, nq, K, seed=500 + 3 * sum(ls) + (K if isinstance(K, int) else 9),
+                           exp_range=(0.05, 200.0))
+    D = inputs.ket_densities(b, seed=77)
+    I = oracle.eri_md4(ls, b.centers, b.exps, b.coefs, b.nprim)
+    check(run(torch, b, D), I, D)
+
+
+def test_matches_contracting_the_librarys_own_integrals_at_full_size(torch):
+    """(ii|ii), K=1, the 512-quartet benchmark batch: J from eri4_batch_coulomb
+    equals the contraction of eri4_batch's integrals (checked against the
+    oracle elsewhere) on every quartet."""
+    b = inputs.iiii(K=1)
+    D = inputs.ket_densities(b, seed=78)
+    C, E, Co, N = dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs), dev(torch, b.nprim)
+    g = eri4.batch_coulomb(b.ls, C, E, Co, N, dev(torch, D))
+    I = eri4.batch(b.ls, C, E, Co, N)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    for q0 in range(0, b.nq, 64):
+        check(g[q0:q0 + 64], I[q0:q0 + 64].cpu().numpy(), D[q0:q0 + 64])
+
+
+def test_passes_through_a_small_workspace_give_the_same_result(torch):
+    ls = (4, 5, 5, 4)
+    b = inputs.class_batch(ls, 5, (1, 2), seed=551, exp_range=(0.05, 200.0))
+    D = inputs.ket_densities(b, seed=79)
+    one = run(torch, b, D)
+    w = torch.empty(eri4.coulomb_work_size(ls, b.kmax, 2), dtype=torch.float64, device="cuda")
+    assert np.array_equal(run(torch, b, D, work=w), one)
+
+
+def test_bad_contraction_length_gives_nan_and_others_are_untouched(torch):
+    ls = (2, 1, 2, 2)
+    b = inputs.class_batch(ls, 3, 2, seed=552)
+    D = inputs.ket_densities(b, seed=80)
+    I = oracle.eri_md4(ls, b.centers, b.exps, b.coefs, b.nprim)
+    bad = b.nprim.copy()
+    bad[1, 3] = 0
+    out = eri4.batch_coulomb(ls, dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs), dev(torch, bad),
+                             dev(torch, D))
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    assert np.isnan(out[1]).all()
+    check(out[[0, 2]], I[[0, 2]], D[[0, 2]])
