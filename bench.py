@@ -282,6 +282,22 @@ def time_pairs(nbra=128, nket=128, kmax=3, reps=3):
     solid_rec = {"value": ps.output_size / ts, "unit": "integrals/s", "ms_per_step": ts * 1e3,
                  "pct_fp64_peak": 100 * sflops / ts / 1e12 / FP64_PEAK_TFLOPS, "workspace_bytes": ps.work_size * 8}
     del work, sout
+    # Coulomb contraction over the same lists: J of every bra entry
+    rng = np.random.default_rng(1203)
+    kd = d(np.concatenate([rng.uniform(-1.0, 1.0, size=metrics.ncart(int(ket.l[j, 0])) * metrics.ncart(int(ket.l[j, 1])))
+                           for j in range(nket)]))
+    pc = eri4.CoulombPlan(bra.l, bra.nprim, ket.l, ket.nprim, kmax)
+    cwork = torch.empty(max(1, pc.work_size), dtype=torch.float64, device="cuda")
+    cout = pc.execute(*args, kd, work=cwork)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pc.execute(*args, kd, out=cout, work=cwork)
+    torch.cuda.synchronize()
+    tc = (time.perf_counter() - t0) / reps
+    coul_rec = {"ms_per_step": tc * 1e3, "integrals_contracted_per_s": pp.output_size / tc,
+                "output_bytes": pc.output_size * 8, "workspace_bytes": pc.work_size * 8}
+    del cwork, cout
     _, qout, tq = time_plan(b, "fp64", reps, 1, tiles)
     flops = md4_flops_batch(b.lq, b.nprim)
     return {"workload": "bra list x ket list: %d x %d shell pairs, l in {4,5,6} per shell, K per shell 1..%d"
@@ -291,7 +307,7 @@ def time_pairs(nbra=128, nket=128, kmax=3, reps=3):
             "quartet_plan_ms_per_step": tq * 1e3, "bitwise_equal_to_quartet_plan": bool(torch.equal(out, qout)),
             "input_bytes": int(sum(a.numel() * 8 for a in args)),
             "quartet_plan_input_bytes": int((b.centers.size + b.exps.size + b.coefs.size) * 8),
-            "solid": solid_rec}
+            "solid": solid_rec, "coulomb": coul_rec}
 
 
 def time_solid(reps=3):
@@ -399,6 +415,15 @@ def time_coulomb(reps=3):
             eri4.batch_coulomb(b.ls, C, E, Co, N, Dd, work=work, out=o)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / reps
+        # the integrals themselves on the same batch, for comparison
+        ints = eri4.batch(b.ls, C, E, Co, N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eri4.batch(b.ls, C, E, Co, N, out=ints)
+        torch.cuda.synchronize()
+        t_ints = (time.perf_counter() - t0) / reps
+        del ints
         kb = K * K
         npp = metrics.nherm(12)
         flops = nq * (2 * 784 * (kb * npp) * (kb * npp) + 2 * 784 * kb * npp + 2 * kb * npp * 784)
@@ -408,7 +433,7 @@ def time_coulomb(reps=3):
         g = o[:2].cpu().numpy()
         err = max(float(np.abs(g[i] - ref[i]).max() / bound[i].max()) for i in range(2))
         out.append({"workload": "(ii|ii) Coulomb contraction J_ab = sum_cd (ab|cd) D_cd, K=%d per shell, %d quartets"
-                                % (K, nq), "ms_per_step": t * 1e3,
+                                % (K, nq), "ms_per_step": t * 1e3, "integrals_ms_per_step_same_batch": t_ints * 1e3,
                     "pct_fp64_peak": 100 * flops / t / 1e12 / FP64_PEAK_TFLOPS,
                     "output_bytes": nq * 784 * 8, "integrals_contracted_per_s": nq * 784 * 784 / t,
                     "parity_max_err_2q_rel_contraction_bound": err})

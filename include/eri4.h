@@ -290,6 +290,33 @@ eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, c
                                     int64_t work_size, double* out, hipStream_t stream);
 
 /*
+ * The Coulomb contraction over a bra and a ket list of shell pairs: for every
+ * bra entry i,
+ *   J_i[ab] = sum_j sum_cd (ab|cd)_ij D_j[cd]
+ * with D_j the density block of ket entry j.  dket of each ket entry is built
+ * once per execute and shared by every bra entry; each quartet's J rows go to
+ * the workspace and are summed over j in a fixed order (reproducible bits).
+ * FP64, Cartesian; the library picks the tiles.
+ * eri4_plan_create_coulomb: host arrays as eri4_plan_create_pairs.
+ * eri4_plan_execute_coulomb: lists as eri4_plan_execute_pairs, and
+ *   ket_dens  device double, the blocks D_j[Nc][Nd] of the ket entries one after
+ *             the other in list order
+ *   work      device double [work_size >= eri4_plan_work_size(plan)]
+ *   out       device double, the blocks J_i[Na][Nb] one after the other in list
+ *             order (eri4_plan_output_size doubles; eri4_plan_output_offsets
+ *             gives the nbra block offsets)
+ * Other plan calls apply (destroy, output size and offsets); the other execute
+ * calls reject a Coulomb plan.
+ */
+eri4_status eri4_plan_create_coulomb(eri4_plan* plan, int64_t nbra, const int32_t* bra_l, const int32_t* bra_nprim,
+                                     int64_t nket, const int32_t* ket_l, const int32_t* ket_nprim, int kmax);
+eri4_status eri4_plan_execute_coulomb(eri4_plan plan, const double* bra_centers, const double* bra_exponents,
+                                      const double* bra_coeffs, const double* ket_centers,
+                                      const double* ket_exponents, const double* ket_coeffs, const double* ket_dens,
+                                      double* work, int64_t work_size, double* out, hipStream_t stream);
+
+
+/*
  * Stage entry points.  They run the same device code the fused eri4_batch
  * kernel runs for one stage, so each stage can be checked on its own.
  */

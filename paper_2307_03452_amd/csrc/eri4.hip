@@ -151,6 +151,7 @@ eri4_status set_attrs() {
   HIP_TRY(solid_set_attrs());
   HIP_TRY(plan_solid_set_attrs());
   HIP_TRY(coulomb_set_attrs());
+  HIP_TRY(plan_coulomb_set_attrs());
   HIP_TRY(plan_set_attrs_f64());
   HIP_TRY(plan_set_attrs_f32());
   HIP_TRY(plan_set_attrs_f64p());
@@ -479,6 +480,13 @@ struct eri4_plan_s {
   int32_t* d_pl = nullptr;   // per list entry: l of its two shells (bra entries first)
   int32_t* d_pn = nullptr;   // per list entry: contraction lengths
   int64_t* d_hoff = nullptr; // per list entry: where its H matrices start in the workspace
+  bool coul = false;         // Coulomb contraction over the lists (eri4_plan_create_coulomb)
+  int64_t dket_size = 0;     // doubles of the workspace holding the ket entries' dket
+  int64_t ket_dens_size = 0; // doubles of ket_dens (all ket entries' blocks)
+  std::vector<int64_t> ooff; // output offsets per bra entry (Coulomb plans)
+  int64_t* d_doff = nullptr;   // per ket entry: its density block in ket_dens
+  int64_t* d_dkoff = nullptr;  // per ket entry: its dket in the workspace
+  int64_t* d_joff = nullptr;   // per bra entry: its J block in out
   int64_t out_size = 0;
   std::vector<int64_t> qoff;
   ClassParams* d_classes = nullptr;
@@ -498,6 +506,9 @@ static void plan_free(eri4_plan_s* p) {
   if (p->d_pl) (void)hipFree(p->d_pl);
   if (p->d_pn) (void)hipFree(p->d_pn);
   if (p->d_hoff) (void)hipFree(p->d_hoff);
+  if (p->d_doff) (void)hipFree(p->d_doff);
+  if (p->d_dkoff) (void)hipFree(p->d_dkoff);
+  if (p->d_joff) (void)hipFree(p->d_joff);
   delete p;
 }
 
@@ -513,7 +524,7 @@ static_assert(ERI4_LAYOUT_BOX == kLayBox && ERI4_LAYOUT_SLAB == kLaySlab && ERI4
 // bra and a ket list (quartet q = bra pair q / nket with ket pair q % nket).
 static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim, int kmax,
                                eri4_precision precision, const eri4_tile_choice* choices, int nchoices, bool pairs,
-                               int64_t nbra, int64_t nket, bool solid) {
+                               int64_t nbra, int64_t nket, bool solid, bool coul = false) {
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
   *plan = nullptr;
   if (precision != ERI4_PREC_FP64 && precision != ERI4_PREC_FP32)
@@ -564,6 +575,9 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
   p->nbra = nbra;
   p->nket = nket;
   p->solid = solid;
+  p->coul = coul;
+  // dynamic LDS available next to the persistent kernel's static LDS
+  const int limit = coul ? kMaxLdsBytes - kCoulLds * 8 - 512 : kMaxLdsBytes - 64;
 
   // groups of quartets with the same class and tile choice (the first matching
   // entry of the table, or none), keyed by class * (nchoices + 1) + entry + 1
@@ -597,12 +611,12 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
     const auto& k = keys[c];
     if (k[4] >= 0) {
       const eri4_tile_choice& ch = choices[k[4]];
-      if (!try_params(k[0], k[1], k[2], k[3], kmax, ch.rows16, ch.layout, d, kMaxLdsBytes - 64, &cps[c])) {
+      if (!try_params(k[0], k[1], k[2], k[3], kmax, ch.rows16, ch.layout, d, limit, &cps[c])) {
         plan_free(p);
         return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile choice %d (rows16 %d, layout %d) does not fit class (%d %d|%d %d)",
                     k[4], ch.rows16, ch.layout, k[0], k[1], k[2], k[3]);
       }
-    } else if (!pick_params(k[0], k[1], k[2], k[3], kmax, d, kMaxLdsBytes - 64, &cps[c])) {
+    } else if (!pick_params(k[0], k[1], k[2], k[3], kmax, d, limit, &cps[c])) {
       plan_free(p);
       return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", k[0], k[1], k[2], k[3]);
     }
@@ -620,7 +634,7 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
   for (int64_t q = 0; q < nquartets; ++q) {
     const ClassParams& c = cps[qcls[q]];
     p->qoff[q] = off;
-    off += (int64_t)c.nab * c.ncd;
+    off += coul ? (int64_t)c.nab : (int64_t)c.nab * c.ncd;  // Coulomb plans: J rows per quartet
     const double kb = (double)nprim[4 * q] * nprim[4 * q + 1], kk = (double)nprim[4 * q + 2] * nprim[4 * q + 3];
     for (int rt = 0; rt < c.nrt; ++rt) {
       const int rows = 16 * std::min(c.rb, (c.nab - rt * c.rb * 16 + 15) / 16);
@@ -646,7 +660,8 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
 
   int ncu = 0, per_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
-  const hipError_t oe = p->solid ? plan_solid_occupancy(p->lds_bytes, &per_cu)
+  const hipError_t oe = p->coul ? plan_coulomb_occupancy(p->lds_bytes, &per_cu)
+                        : p->solid ? plan_solid_occupancy(p->lds_bytes, &per_cu)
                         : p->pairs ? (p->f32 ? plan_occupancy_f32p(p->lds_bytes, &per_cu)
                                            : plan_occupancy_f64p(p->lds_bytes, &per_cu))
                                  : (p->f32 ? plan_occupancy_f32(p->lds_bytes, &per_cu)
@@ -691,8 +706,9 @@ int64_t eri4_plan_output_size(eri4_plan plan) { return plan ? plan->out_size : -
 eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets) {
   g_err.clear();
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
-  if (plan->nq > 0 && !offsets) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL offsets array");
-  std::copy(plan->qoff.begin(), plan->qoff.end(), offsets);
+  const std::vector<int64_t>& o = plan->coul ? plan->ooff : plan->qoff;
+  if (!o.empty() && !offsets) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL offsets array");
+  std::copy(o.begin(), o.end(), offsets);
   return ERI4_SUCCESS;
 }
 
@@ -807,6 +823,109 @@ eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t*
 
 int64_t eri4_plan_work_size(eri4_plan plan) { return plan ? plan->work : -1; }
 
+eri4_status eri4_plan_create_coulomb(eri4_plan* plan, int64_t nbra, const int32_t* bra_l, const int32_t* bra_nprim,
+                                     int64_t nket, const int32_t* ket_l, const int32_t* ket_nprim, int kmax) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
+  *plan = nullptr;
+  if (nbra < 0 || nket < 0) return fail(ERI4_ERROR_INVALID_ARGUMENT, "negative list length");
+  if (nbra > 0 && nket > (((int64_t)1 << 31) - 1) / nbra)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "nbra * nket must be below 2^31");
+  if ((nbra > 0 && (!bra_l || !bra_nprim)) || (nket > 0 && (!ket_l || !ket_nprim)))
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL host array");
+  const int64_t nq = nbra * nket;
+  std::vector<int32_t> l(4 * nq), np(4 * nq);
+  for (int64_t i = 0; i < nbra; ++i)
+    for (int64_t j = 0; j < nket; ++j) {
+      const int64_t q = i * nket + j;
+      l[4 * q] = bra_l[2 * i], l[4 * q + 1] = bra_l[2 * i + 1];
+      l[4 * q + 2] = ket_l[2 * j], l[4 * q + 3] = ket_l[2 * j + 1];
+      np[4 * q] = bra_nprim[2 * i], np[4 * q + 1] = bra_nprim[2 * i + 1];
+      np[4 * q + 2] = ket_nprim[2 * j], np[4 * q + 3] = ket_nprim[2 * j + 1];
+    }
+  eri4_status st = plan_create(plan, nq, l.data(), np.data(), kmax, ERI4_PREC_FP64, nullptr, 0, true, nbra, nket,
+                               false, true);
+  if (st != ERI4_SUCCESS) return st;
+  eri4_plan_s* p = *plan;
+  // workspace: dket of every ket entry (kmax^2 slots), then the quartets' J rows
+  const int64_t ne = nbra + nket;
+  std::vector<int32_t> pl(2 * ne), pn(2 * ne);
+  std::vector<int64_t> doff(std::max<int64_t>(1, nket)), dkoff(std::max<int64_t>(1, nket)), joff(nbra);
+  for (int64_t e = 0; e < ne; ++e) {
+    const bool ket = e >= nbra;
+    const int64_t i = ket ? e - nbra : e;
+    pl[2 * e] = (ket ? ket_l : bra_l)[2 * i], pl[2 * e + 1] = (ket ? ket_l : bra_l)[2 * i + 1];
+    pn[2 * e] = (ket ? ket_nprim : bra_nprim)[2 * i], pn[2 * e + 1] = (ket ? ket_nprim : bra_nprim)[2 * i + 1];
+  }
+  int64_t od = 0, ok_ = 0, oj = 0;
+  for (int64_t j = 0; j < nket; ++j) {
+    const int lc = ket_l[2 * j], ld = ket_l[2 * j + 1];
+    doff[j] = od;
+    od += (int64_t)ncart(lc) * ncart(ld);
+    dkoff[j] = ok_;
+    ok_ += (int64_t)kmax * kmax * 16 * ((nherm(lc + ld) + 15) / 16);
+  }
+  for (int64_t i = 0; i < nbra; ++i) {
+    joff[i] = oj;
+    oj += (int64_t)ncart(bra_l[2 * i]) * ncart(bra_l[2 * i + 1]);
+  }
+  p->dket_size = ok_;
+  p->work = ok_ + p->out_size;  // out_size so far: the quartets' J rows
+  p->out_size = oj;
+  p->ooff = joff;
+  p->ket_dens_size = od;
+  const bool ok = hipMalloc(&p->d_pl, std::max<int64_t>(1, 2 * ne) * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(&p->d_pn, std::max<int64_t>(1, 2 * ne) * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(&p->d_doff, doff.size() * sizeof(int64_t)) == hipSuccess &&
+                  hipMalloc(&p->d_dkoff, dkoff.size() * sizeof(int64_t)) == hipSuccess &&
+                  hipMalloc(&p->d_joff, std::max<int64_t>(1, nbra) * sizeof(int64_t)) == hipSuccess;
+  hipError_t e = ok ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_pl, pl.data(), 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_pn, pn.data(), 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_doff, doff.data(), doff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_dkoff, dkoff.data(), dkoff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && nbra > 0) e = hipMemcpy(p->d_joff, joff.data(), nbra * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    plan_free(p);
+    *plan = nullptr;
+    return ok ? fail(ERI4_ERROR_HIP, "plan upload: %s", hipGetErrorString(e))
+              : fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation for the plan failed");
+  }
+  return ERI4_SUCCESS;
+}
+
+eri4_status eri4_plan_execute_coulomb(eri4_plan plan, const double* bra_centers, const double* bra_exponents,
+                                      const double* bra_coeffs, const double* ket_centers,
+                                      const double* ket_exponents, const double* ket_coeffs, const double* ket_dens,
+                                      double* work, int64_t work_size, double* out, hipStream_t stream) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (!plan->coul) return fail(ERI4_ERROR_INVALID_ARGUMENT, "not a Coulomb plan (eri4_plan_create_coulomb)");
+  if (plan->nitems == 0) return ERI4_SUCCESS;
+  if (!bra_centers || !bra_exponents || !bra_coeffs || !ket_centers || !ket_exponents || !ket_coeffs || !ket_dens ||
+      !out)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  if (!work || work_size < plan->work)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below the plan's %lld",
+                (long long)(work ? work_size : 0), (long long)plan->work);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != plan->device)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan was made for device %d, current device is %d", plan->device, dev);
+  DeviceState* d;
+  eri4_status st = ensure_device(&d);
+  if (st != ERI4_SUCCESS) return st;
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, plan->d_counter);
+  HIP_TRY(hipGetLastError());
+  const Shells shl{bra_centers, bra_exponents, bra_coeffs, ket_centers, ket_exponents, ket_coeffs, plan->nket};
+  const PlanArgs a{plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter, shl,
+                   nullptr};
+  HIP_TRY(plan_coulomb_launch(dim3(plan->grid), plan->lds_bytes, stream, Tables{d->boys, d->rtab}, a,
+                              (int)plan->nbra, plan->kmax, plan->d_pl, plan->d_pn, ket_dens, plan->d_doff,
+                              plan->d_dkoff, plan->d_joff, work, work + plan->dket_size, out));
+  return ERI4_SUCCESS;
+}
+
 eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, const double* bra_exponents,
                                     const double* bra_coeffs, const double* ket_centers,
                                     const double* ket_exponents, const double* ket_coeffs, double* work,
@@ -814,6 +933,7 @@ eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, c
   g_err.clear();
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
   if (!plan->pairs) return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan made from quartets: use eri4_plan_execute");
+  if (plan->coul) return fail(ERI4_ERROR_INVALID_ARGUMENT, "Coulomb plan: use eri4_plan_execute_coulomb");
   return plan_launch(plan,
                      Shells{bra_centers, bra_exponents, bra_coeffs, ket_centers, ket_exponents, ket_coeffs,
                             plan->nket},

@@ -76,6 +76,12 @@ hipError_t plan_solid_set_attrs();
 hipError_t plan_solid_occupancy(int lds_bytes, int* per_cu);
 hipError_t plan_solid_launch(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a,
                              int64_t nbra, const int64_t* hoff, const double* h);
+hipError_t plan_coulomb_set_attrs();
+hipError_t plan_coulomb_occupancy(int lds_bytes, int* per_cu);
+hipError_t plan_coulomb_launch(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a,
+                               int nbra, int kmax, const int32_t* pl, const int32_t* pn, const double* ket_dens,
+                               const int64_t* doff, const int64_t* dkoff, const int64_t* joff, double* dket,
+                               double* jpart, double* out);
 hipError_t solid_hpairs_launch(int nbra, int nket, int kmax, hipStream_t s, const int32_t* pl, const int32_t* pn,
                                const Shells& x, const int64_t* hoff, const double* stab, double* h);
 

@@ -50,6 +50,7 @@ STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UN
 EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version", "eri4_init",
            "eri4_batch", "eri4_plan_create", "eri4_plan_create_tuned", "eri4_plan_output_size", "eri4_plan_output_offsets",
            "eri4_plan_execute", "eri4_plan_destroy", "eri4_plan_create_pairs", "eri4_plan_execute_pairs", "eri4_plan_work_size",
+           "eri4_plan_create_coulomb", "eri4_plan_execute_coulomb",
            "eri4_boys", "eri4_hermite_r", "eri4_hermite_e", "eri4_solid_coefficients", "eri4_solid_work_size",
            "eri4_batch_solid", "eri4_coulomb_work_size", "eri4_batch_coulomb")
 
@@ -105,6 +106,10 @@ def lib() -> ctypes.CDLL:
         L.eri4_plan_create_pairs.argtypes = [ctypes.POINTER(vp), i64, vp, vp, i64, vp, vp, c_int, c_int, c_int, vp,
                                              c_int]
         L.eri4_plan_create_pairs.restype = c_int
+        L.eri4_plan_create_coulomb.argtypes = [ctypes.POINTER(vp), i64, vp, vp, i64, vp, vp, c_int]
+        L.eri4_plan_create_coulomb.restype = c_int
+        L.eri4_plan_execute_coulomb.argtypes = [vp] * 8 + [vp, i64, vp, vp]
+        L.eri4_plan_execute_coulomb.restype = c_int
         L.eri4_plan_work_size.argtypes = [vp]
         L.eri4_plan_work_size.restype = i64
         L.eri4_plan_execute_pairs.argtypes = [vp] * 7 + [vp, i64, vp, vp]
@@ -386,4 +391,48 @@ class PairPlan(Plan):
             self._h, _ptr(bra_centers, "float64"), _ptr(bra_exps, "float64"), _ptr(bra_coefs, "float64"),
             _ptr(ket_centers, "float64"), _ptr(ket_exps, "float64"), _ptr(ket_coefs, "float64"),
             _ptr(work, "float64"), work.numel() if work is not None else 0, _ptr(out, "float64"), _stream(stream)))
+        return out
+
+
+class CoulombPlan(Plan):
+    """J_i = sum_j sum_cd (ab|cd)_ij D_j[cd] for every bra entry i of a bra list
+    and a ket list of shell pairs (eri4_plan_*_coulomb).  Host int32 arrays as
+    PairPlan; execute() takes the device lists, ket_dens (the ket entries'
+    blocks D_j[Nc][Nd] one after the other) and returns the bra entries' blocks
+    J_i[Na][Nb] one after the other (offsets(): where each starts)."""
+
+    def __init__(self, bra_l, bra_nprim, ket_l, ket_nprim, kmax: int):
+        import numpy as np
+        bl, bn = (np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 2) for a in (bra_l, bra_nprim))
+        kl, kn = (np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 2) for a in (ket_l, ket_nprim))
+        self.nbra, self.nket = bl.shape[0], kl.shape[0]
+        self.nq = self.nbra * self.nket
+        self.kmax = int(kmax)
+        h = ctypes.c_void_p()
+        vp = ctypes.c_void_p
+        _check(lib().eri4_plan_create_coulomb(ctypes.byref(h), self.nbra, bl.ctypes.data_as(vp), bn.ctypes.data_as(vp),
+                                              self.nket, kl.ctypes.data_as(vp), kn.ctypes.data_as(vp), self.kmax))
+        self._h = h
+
+    @property
+    def work_size(self) -> int:
+        return lib().eri4_plan_work_size(self._h)
+
+    def offsets(self):
+        import numpy as np
+        off = np.zeros(self.nbra, dtype=np.int64)
+        _check(lib().eri4_plan_output_offsets(self._h, off.ctypes.data_as(ctypes.c_void_p)))
+        return off
+
+    def execute(self, bra_centers, bra_exps, bra_coefs, ket_centers, ket_exps, ket_coefs, ket_dens, out=None,
+                work=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(max(1, self.output_size), dtype=torch.float64, device=bra_centers.device)
+        if work is None:
+            work = torch.empty(max(1, self.work_size), dtype=torch.float64, device=bra_centers.device)
+        _check(lib().eri4_plan_execute_coulomb(
+            self._h, _ptr(bra_centers, "float64"), _ptr(bra_exps, "float64"), _ptr(bra_coefs, "float64"),
+            _ptr(ket_centers, "float64"), _ptr(ket_exps, "float64"), _ptr(ket_coefs, "float64"),
+            _ptr(ket_dens, "float64"), _ptr(work, "float64"), work.numel(), _ptr(out, "float64"), _stream(stream)))
         return out

@@ -250,3 +250,18 @@ def test_coulomb_work_size_and_host_errors():
     assert b"workspace" in L.eri4_last_error()
     assert L.eri4_batch_coulomb(2, 2, 2, 2, 4, p, p, p, p, 1, None, p, 10 ** 6, p, None) == STATUS_INVALID
     assert L.eri4_batch_coulomb(2, 2, 2, 2, 0, None, None, None, None, 1, None, None, 0, None, None) == 0
+
+
+def test_coulomb_plan_create_rejects_bad_host_arrays():
+    import numpy as np
+    L = eri4.lib()
+    h = ctypes.c_void_p()
+    bl, bn = np.full((2, 2), 4, np.int32), np.ones((2, 2), np.int32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert L.eri4_plan_create_coulomb(None, 2, ptr(bl), ptr(bn), 2, ptr(bl), ptr(bn), 1) == STATUS_INVALID
+    assert L.eri4_plan_create_coulomb(ctypes.byref(h), -2, ptr(bl), ptr(bn), 2, ptr(bl), ptr(bn), 1) == STATUS_INVALID
+    assert L.eri4_plan_create_coulomb(ctypes.byref(h), 2, None, ptr(bn), 2, ptr(bl), ptr(bn), 1) == STATUS_INVALID
+    bad = bl.copy(); bad[1, 1] = 9
+    assert L.eri4_plan_create_coulomb(ctypes.byref(h), 2, ptr(bad), ptr(bn), 2, ptr(bl), ptr(bn), 1) == STATUS_UNSUPPORTED
+    assert h.value is None
+    assert L.eri4_plan_execute_coulomb(None, *([None] * 7), None, 0, None, None) == STATUS_INVALID

@@ -90,3 +90,55 @@ def test_bad_contraction_length_gives_nan_and_others_are_untouched(torch):
     out = out.cpu().numpy()
     assert np.isnan(out[1]).all()
     check(out[[0, 2]], I[[0, 2]], D[[0, 2]])
+
+
+def _list_densities(ket, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.uniform(-1.0, 1.0, size=(inputs.ncart(int(ket.l[j, 0])), inputs.ncart(int(ket.l[j, 1]))))
+            for j in range(ket.n)]
+
+
+def test_coulomb_pair_plan_against_oracle(torch):
+    """J_i = sum_j sum_cd (ab|cd)_ij D_j over a 4-entry bra list and a 5-entry
+    ket list with l in {2, 3, 4} and contraction lengths 1..2."""
+    bra = inputs.pair_list(4, 61, lvals=(2, 3, 4), kmax=2)
+    ket = inputs.pair_list(5, 62, lvals=(2, 3, 4), kmax=2)
+    Ds = _list_densities(ket, 63)
+    p = eri4.CoulombPlan(bra.l, bra.nprim, ket.l, ket.nprim, 2)
+    d = lambda a: dev(torch, a)
+    kd = d(np.concatenate([x.ravel() for x in Ds]))
+    args = (d(bra.centers), d(bra.exps), d(bra.coefs), d(ket.centers), d(ket.exps), d(ket.coefs), kd)
+    g = p.execute(*args)
+    g2 = p.execute(*args)
+    torch.cuda.synchronize()
+    g, g2 = g.cpu().numpy(), g2.cpu().numpy()
+    assert np.array_equal(g, g2)  # fixed summation order
+    off = p.offsets()
+    b = inputs.expand_pairs(bra, ket)
+    for i in range(bra.n):
+        na, nb = inputs.ncart(int(bra.l[i, 0])), inputs.ncart(int(bra.l[i, 1]))
+        ref = np.zeros((na, nb))
+        bound = np.zeros((na, nb))
+        for j in range(ket.n):
+            q = i * ket.n + j
+            s = inputs.subset(b, [q])
+            I = oracle.eri_md4(tuple(int(x) for x in b.lq[q]), s.centers, s.exps, s.coefs, s.nprim)[0]
+            ref += np.einsum("abcd,cd->ab", I, Ds[j])
+            bound += np.einsum("abcd,cd->ab", np.abs(I), np.abs(Ds[j]))
+        got = g[off[i]:off[i] + na * nb].reshape(na, nb)
+        assert np.abs(got - ref).max() <= TOL * bound.max(), (i, np.abs(got - ref).max() / bound.max())
+
+
+def test_coulomb_pair_plan_rejects_other_executes_and_small_workspaces(torch):
+    bra, ket = inputs.pair_list(2, 64, kmax=1), inputs.pair_list(2, 65, kmax=1)
+    p = eri4.CoulombPlan(bra.l, bra.nprim, ket.l, ket.nprim, 1)
+    d = lambda a: dev(torch, a)
+    kd = d(np.concatenate([x.ravel() for x in _list_densities(ket, 66)]))
+    args = (d(bra.centers), d(bra.exps), d(bra.coefs), d(ket.centers), d(ket.exps), d(ket.coefs))
+    with pytest.raises(eri4.Eri4Error, match="workspace"):
+        p.execute(*args, kd, work=torch.empty(p.work_size - 1, dtype=torch.float64, device="cuda"))
+    L = eri4.lib()
+    out = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    ptr = lambda t: t.data_ptr()
+    assert L.eri4_plan_execute_pairs(p._h, *(ptr(a) for a in args), None, 0, ptr(out), None) == 1
+    assert b"Coulomb" in L.eri4_last_error()
