@@ -142,3 +142,41 @@ def test_coulomb_pair_plan_rejects_other_executes_and_small_workspaces(torch):
     ptr = lambda t: t.data_ptr()
     assert L.eri4_plan_execute_pairs(p._h, *(ptr(a) for a in args), None, 0, ptr(out), None) == 1
     assert b"Coulomb" in L.eri4_last_error()
+
+
+def test_solid_batch_and_coulomb_plan_replay_in_a_hip_graph(torch):
+    """eri4_batch_solid and a Coulomb pair-list plan captured in one HIP graph
+    (no allocation, no memset nodes) give the eager results on every replay,
+    with unrelated eager work between replays."""
+    ls = (4, 4, 5, 4)
+    b = inputs.class_batch(ls, 3, 2, seed=571, exp_range=(0.05, 200.0))
+    C, E, Co, N = dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs), dev(torch, b.nprim)
+    work = torch.empty(eri4.solid_work_size(ls, 2, 3), dtype=torch.float64, device="cuda")
+    eager_s = eri4.batch_solid(ls, C, E, Co, N, work=work).clone()
+    bra, ket = inputs.pair_list(3, 572, lvals=(2, 4), kmax=2), inputs.pair_list(3, 573, lvals=(3, 4), kmax=2)
+    Ds = _list_densities(ket, 574)
+    p = eri4.CoulombPlan(bra.l, bra.nprim, ket.l, ket.nprim, 2)
+    d = lambda a: dev(torch, a)
+    args = (d(bra.centers), d(bra.exps), d(bra.coefs), d(ket.centers), d(ket.exps), d(ket.coefs),
+            d(np.concatenate([x.ravel() for x in Ds])))
+    cwork = torch.empty(p.work_size, dtype=torch.float64, device="cuda")
+    eager_c = p.execute(*args, work=cwork).clone()
+    torch.cuda.synchronize()
+    out_s = torch.zeros_like(eager_s)
+    out_c = torch.zeros_like(eager_c)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        eri4.batch_solid(ls, C, E, Co, N, work=work, out=out_s, stream=s)
+        p.execute(*args, out=out_c, work=cwork, stream=s)
+    for rep in range(3):
+        out_s.zero_()
+        out_c.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_s, eager_s), rep
+        assert torch.equal(out_c, eager_c), rep
+        eri4.batch(ls, C[:1].contiguous(), E[:1].contiguous(), Co[:1].contiguous(), N[:1].contiguous())
+        torch.cuda.synchronize()
