@@ -147,7 +147,7 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets,
  * workspace holds: eri4_solid_work_size(la, lb, lc, ld, kmax, n) doubles hold
  * n quartets (-1 for bad arguments); a workspace below one quartet's size gives
  * INVALID_ARGUMENT.  FP64 throughout; enqueue-only (nothing is allocated
- * after the first call on a device).
+ * after the first call on a device), so a HIP graph can capture it.
  */
 /*
  * Coulomb contraction without forming (ab|cd): for every quartet,
@@ -306,7 +306,8 @@ eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, c
  *             order (eri4_plan_output_size doubles; eri4_plan_output_offsets
  *             gives the nbra block offsets)
  * Other plan calls apply (destroy, output size and offsets); the other execute
- * calls reject a Coulomb plan.
+ * calls reject a Coulomb plan.  Execute is enqueue-only and capturable, as
+ * eri4_plan_execute.
  */
 eri4_status eri4_plan_create_coulomb(eri4_plan* plan, int64_t nbra, const int32_t* bra_l, const int32_t* bra_nprim,
                                      int64_t nket, const int32_t* ket_l, const int32_t* ket_nprim, int kmax);
