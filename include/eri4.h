@@ -247,7 +247,7 @@ eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int
                                    int kmax, eri4_precision precision, const eri4_tile_choice* choices,
                                    int nchoices);
 int64_t eri4_plan_output_size(eri4_plan plan);                         /* doubles; -1 if plan is NULL */
-eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets); /* HOST int64 [nquartets] */
+eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets); /* HOST int64 [nquartets]; Coulomb plans: [nbra] */
 eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents,
                               const double* coeffs, double* out, hipStream_t stream);
 eri4_status eri4_plan_destroy(eri4_plan plan);
