@@ -27,7 +27,7 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int32)
         L.oracle_boys.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.oracle_boys.restype = None
-        for name in ("oracle_eri_md4", "oracle_eri_os"):
+        for name in ("oracle_eri_md4", "oracle_eri_os", "oracle_eri_md4_quad"):
             f = getattr(L, name)
             f.argtypes = [ctypes.c_int] * 4 + [ctypes.c_int64, dp, dp, dp, ip, ctypes.c_int, dp, ctypes.c_int]
             f.restype = ctypes.c_int
@@ -80,6 +80,13 @@ def _eri(fn, ls, centers, exps, coefs, nprim, nthreads):
 def eri_md4(ls, centers, exps, coefs, nprim, nthreads=0):
     """(ab|cd) by the paper's McMurchie-Davidson scheme, plain scalar form."""
     return _eri(lib().oracle_eri_md4, ls, centers, exps, coefs, nprim, nthreads)
+
+
+def eri_md4_quad(ls, centers, exps, coefs, nprim, nthreads=0):
+    """(ab|cd) by the same scheme as eri_md4 with every step in __float128 and
+    the result rounded to double: truth values that measure eri_md4's own
+    rounding error (slow; for small samples)."""
+    return _eri(lib().oracle_eri_md4_quad, ls, centers, exps, coefs, nprim, nthreads)
 
 
 def eri_os(ls, centers, exps, coefs, nprim, nthreads=0):

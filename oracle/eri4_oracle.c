@@ -560,3 +560,206 @@ int oracle_max_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Quad-precision instance of the McMurchie-Davidson scheme (truth values).   */
+/*                                                                            */
+/* The same steps as md4_primitive above (Sec. 2: the E recursions after      */
+/* eq. (cart2herm-2), [0]^(m) from eq. (boys), eq. (md1), eq. (pq), then       */
+/* eqs. (ab_to_hermite) and (cd_to_hermite)), every quantity in __float128:   */
+/* the inputs are converted exactly, the Boys function is kept in quad, and   */
+/* only the final sums are rounded to double.  Its rounding error is ~1e-30   */
+/* of the terms' size, so it measures the FP64 oracle's own error on the same */
+/* inputs.  Slow (software arithmetic): for subsamples only.                  */
+/* ------------------------------------------------------------------------ */
+
+typedef __float128 quad;
+
+static void boys_q(int mmax, quad x, quad* F) {
+  if (mmax < 0) return;
+  quad ex = expq(-x);
+  if (x < 50) {
+    quad term = 1.0Q / (2 * mmax + 1);
+    quad sum = term;
+    for (int k = 1; k < 100000; ++k) {
+      term *= 2 * x / (2 * mmax + 2 * k + 1);
+      sum += term;
+      if (term < sum * 1e-36Q) break;
+    }
+    quad f = ex * sum;
+    F[mmax] = f;
+    for (int m = mmax - 1; m >= 0; --m) {
+      f = (2 * x * f + ex) / (2 * m + 1);
+      F[m] = f;
+    }
+  } else {
+    quad f = 0.5Q * sqrtq(M_PIq / x) * erfq(sqrtq(x));
+    F[0] = f;
+    for (int m = 0; m < mmax; ++m) {
+      f = ((2 * m + 1) * f - ex) / (2 * x);
+      F[m + 1] = f;
+    }
+  }
+}
+
+static void md_etab_axis_q(int la, int lb, quad zp, quad PA, quad PB, quad* E) {
+  const int nt = la + lb + 1;
+#define EIX(a, b, t) (((a) * (lb + 1) + (b)) * nt + (t))
+  for (int i = 0; i < (la + 1) * (lb + 1) * nt; ++i) E[i] = 0;
+  const quad h = 1 / (2 * zp);
+  E[EIX(0, 0, 0)] = 1;
+  for (int a = 0; a < la; ++a)
+    for (int t = 0; t <= a + 1; ++t) {
+      quad v = 0;
+      if (t >= 1) v += h * E[EIX(a, 0, t - 1)];
+      if (t <= a) v += PA * E[EIX(a, 0, t)];
+      if (t + 1 <= a) v += (t + 1) * E[EIX(a, 0, t + 1)];
+      E[EIX(a + 1, 0, t)] = v;
+    }
+  for (int a = 0; a <= la; ++a)
+    for (int b = 0; b < lb; ++b)
+      for (int t = 0; t <= a + b + 1; ++t) {
+        quad v = 0;
+        if (t >= 1) v += h * E[EIX(a, b, t - 1)];
+        if (t <= a + b) v += PB * E[EIX(a, b, t)];
+        if (t + 1 <= a + b) v += (t + 1) * E[EIX(a, b, t + 1)];
+        E[EIX(a, b + 1, t)] = v;
+      }
+#undef EIX
+}
+
+static void md_rtuv_all_q(int L, quad zp, quad zq, const quad* P, const quad* Q, quad* R) {
+  const int n1 = L + 1;
+#define RIX(m, t, u, v) ((((size_t)(m) * n1 + (t)) * n1 + (u)) * n1 + (v))
+  const quad rho = zp * zq / (zp + zq);
+  const quad X[3] = {P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
+  quad F[4 * ORACLE_LMAX + 2];
+  boys_q(L, rho * (X[0] * X[0] + X[1] * X[1] + X[2] * X[2]), F);
+  const quad pref = 2 * powq(M_PIq, 2.5Q) / (zp * zq * sqrtq(zp + zq));
+  quad pw = 1;
+  for (int m = 0; m <= L; ++m) {
+    R[RIX(m, 0, 0, 0)] = pw * pref * F[m];
+    pw *= -2 * rho;
+  }
+  for (int n = 1; n <= L; ++n)
+    for (int t = 0; t <= n; ++t)
+      for (int u = 0; u <= n - t; ++u) {
+        const int v = n - t - u;
+        for (int m = 0; m <= L - n; ++m) {
+          quad val;
+          if (t > 0) {
+            val = X[0] * R[RIX(m + 1, t - 1, u, v)];
+            if (t > 1) val += (t - 1) * R[RIX(m + 1, t - 2, u, v)];
+          } else if (u > 0) {
+            val = X[1] * R[RIX(m + 1, t, u - 1, v)];
+            if (u > 1) val += (u - 1) * R[RIX(m + 1, t, u - 2, v)];
+          } else {
+            val = X[2] * R[RIX(m + 1, t, u, v - 1)];
+            if (v > 1) val += (v - 1) * R[RIX(m + 1, t, u, v - 2)];
+          }
+          R[RIX(m, t, u, v)] = val;
+        }
+      }
+#undef RIX
+}
+
+static void md4_primitive_q(int la, int lb, int lc, int ld, const double* A_, const double* B_, const double* C_,
+                            const double* D_, double za_, double zb_, double zc_, double zd_, quad w, quad* out) {
+  const int Lb = la + lb, Lk = lc + ld, L = Lb + Lk;
+  const int na = oracle_ncart(la), nb = oracle_ncart(lb), nc = oracle_ncart(lc), nd = oracle_ncart(ld);
+  int ca[45][3], cb[45][3], cc[45][3], cd[45][3];
+  cart_list(la, ca);
+  cart_list(lb, cb);
+  cart_list(lc, cc);
+  cart_list(ld, cd);
+  const quad za = za_, zb = zb_, zc = zc_, zd = zd_;
+  const quad zp = za + zb, zq = zc + zd;
+  quad A[3], B[3], C[3], D[3], P[3], Q[3], AB2 = 0, CD2 = 0;
+  for (int i = 0; i < 3; ++i) {
+    A[i] = A_[i], B[i] = B_[i], C[i] = C_[i], D[i] = D_[i];
+    P[i] = (za * A[i] + zb * B[i]) / zp;
+    Q[i] = (zc * C[i] + zd * D[i]) / zq;
+    AB2 += (A[i] - B[i]) * (A[i] - B[i]);
+    CD2 += (C[i] - D[i]) * (C[i] - D[i]);
+  }
+  const quad scale = w * expq(-za * zb / zp * AB2) * expq(-zc * zd / zq * CD2);
+  const size_t nEb = (size_t)(la + 1) * (lb + 1) * (Lb + 1);
+  const size_t nEk = (size_t)(lc + 1) * (ld + 1) * (Lk + 1);
+  quad* Eb = (quad*)malloc(sizeof(quad) * 3 * nEb);
+  quad* Ek = (quad*)malloc(sizeof(quad) * 3 * nEk);
+  for (int i = 0; i < 3; ++i) {
+    md_etab_axis_q(la, lb, zp, P[i] - A[i], P[i] - B[i], Eb + i * nEb);
+    md_etab_axis_q(lc, ld, zq, Q[i] - C[i], Q[i] - D[i], Ek + i * nEk);
+  }
+#define EB(i, a, b, t) Eb[(i) * nEb + ((size_t)(a) * (lb + 1) + (b)) * (Lb + 1) + (t)]
+#define EK(i, c, d, t) Ek[(i) * nEk + ((size_t)(c) * (ld + 1) + (d)) * (Lk + 1) + (t)]
+  const int n1 = L + 1;
+  quad* R = (quad*)calloc((size_t)n1 * n1 * n1 * n1, sizeof(quad));
+  md_rtuv_all_q(L, zp, zq, P, Q, R);
+#define R0(t, u, v) R[((size_t)(t) * n1 + (u)) * n1 + (v)]
+  const int k1 = Lk + 1;
+  const size_t nq3 = (size_t)k1 * k1 * k1;
+  quad* Xq = (quad*)calloc((size_t)na * nb * nq3, sizeof(quad));
+  for (int ia = 0; ia < na; ++ia)
+    for (int ib = 0; ib < nb; ++ib) {
+      const int* a = ca[ia];
+      const int* b = cb[ib];
+      quad* x = Xq + ((size_t)ia * nb + ib) * nq3;
+      for (int tq = 0; tq <= Lk; ++tq)
+        for (int uq = 0; uq <= Lk - tq; ++uq)
+          for (int vq = 0; vq <= Lk - tq - uq; ++vq) {
+            const quad sgn = ((tq + uq + vq) & 1) ? -1 : 1;
+            quad s = 0;
+            for (int tp = 0; tp <= a[0] + b[0]; ++tp)
+              for (int up = 0; up <= a[1] + b[1]; ++up)
+                for (int vp = 0; vp <= a[2] + b[2]; ++vp)
+                  s += EB(0, a[0], b[0], tp) * EB(1, a[1], b[1], up) * EB(2, a[2], b[2], vp) * sgn *
+                       R0(tp + tq, up + uq, vp + vq);
+            x[((size_t)tq * k1 + uq) * k1 + vq] = s;
+          }
+    }
+  for (int iab = 0; iab < na * nb; ++iab) {
+    const quad* x = Xq + (size_t)iab * nq3;
+    for (int ic = 0; ic < nc; ++ic)
+      for (int id = 0; id < nd; ++id) {
+        const int* c = cc[ic];
+        const int* d = cd[id];
+        quad s = 0;
+        for (int tq = 0; tq <= c[0] + d[0]; ++tq)
+          for (int uq = 0; uq <= c[1] + d[1]; ++uq)
+            for (int vq = 0; vq <= c[2] + d[2]; ++vq)
+              s += EK(0, c[0], d[0], tq) * EK(1, c[1], d[1], uq) * EK(2, c[2], d[2], vq) *
+                   x[((size_t)tq * k1 + uq) * k1 + vq];
+        out[(size_t)iab * nc * nd + (size_t)ic * nd + id] += scale * s;
+      }
+  }
+#undef EB
+#undef EK
+#undef R0
+  free(Xq);
+  free(R);
+  free(Eb);
+  free(Ek);
+}
+
+static void md4_quartet_q(int la, int lb, int lc, int ld, const double* ctr, const double* ex, const double* co,
+                          const int32_t* np, int kmax, double* out) {
+  const size_t n = (size_t)oracle_ncart(la) * oracle_ncart(lb) * oracle_ncart(lc) * oracle_ncart(ld);
+  quad* acc = (quad*)calloc(n, sizeof(quad));
+  for (int i = 0; i < np[0]; ++i)
+    for (int j = 0; j < np[1]; ++j)
+      for (int k = 0; k < np[2]; ++k)
+        for (int l = 0; l < np[3]; ++l) {
+          const quad w = (quad)co[0 * kmax + i] * co[1 * kmax + j] * co[2 * kmax + k] * co[3 * kmax + l];
+          md4_primitive_q(la, lb, lc, ld, ctr, ctr + 3, ctr + 6, ctr + 9, ex[0 * kmax + i], ex[1 * kmax + j],
+                          ex[2 * kmax + k], ex[3 * kmax + l], w, acc);
+        }
+  for (size_t i = 0; i < n; ++i) out[i] = (double)acc[i];
+  free(acc);
+}
+
+/* As oracle_eri_md4, every step in __float128, the result rounded to double. */
+int oracle_eri_md4_quad(int la, int lb, int lc, int ld, int64_t nq, const double* centers, const double* exps,
+                        const double* coefs, const int32_t* nprim, int kmax, double* out, int nthreads) {
+  return run_batch(md4_quartet_q, la, lb, lc, ld, nq, centers, exps, coefs, nprim, kmax, out, nthreads);
+}

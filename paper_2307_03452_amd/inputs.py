@@ -67,7 +67,7 @@ def normalize_shells(l, exps, raw, nprim):
     l = np.asarray(l)
     kmax = exps.shape[-1]
     mask = np.arange(kmax) < np.asarray(nprim)[..., None]
-    df = np.vectorize(lambda n: _dfact(2 * int(n) - 1))(l).astype(np.float64)
+    df = np.vectorize(lambda n: _dfact(2 * int(n) - 1), otypes=[np.float64])(l)
     lf = l.astype(np.float64)[..., None]
     nrm = np.sqrt((4.0 * exps) ** lf * (2.0 * exps / np.pi) ** 1.5 / df[..., None])
     c = np.where(mask, raw * nrm, 0.0)
