@@ -567,6 +567,19 @@ def cpu_baseline(wl, b, budget_s=12.0):
                       f"{t_tot:.1f} s"}
 
 
+def calibrate_copy(mib, reps=3):
+    """dst = src + 0.0 on float64 tensors of mib MiB: one elementwise kernel
+    that reads and writes exactly mib MiB per call."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.add(src, 0.0, out=dst)
+    torch.cuda.synchronize()
+    print(f"copied {mib} MiB x {reps}", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -584,7 +597,20 @@ def main():
     ap.add_argument("--solid-steps", type=int, default=3,
                     help="timed calls of each solid-harmonic (ii|ii) batch (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline workload only (every other leg and the CPU baseline off), "
+                         "e.g. for a profiler run whose dispatches must all belong to one workload")
+    ap.add_argument("--calibrate-copy", type=int, metavar="MIB", default=0,
+                    help="instead of benchmarking, run a plain device copy (dst = src + 0) of MIB MiB of "
+                         "float64 three times: the known-size kernel whose FETCH_SIZE/WRITE_SIZE counters "
+                         "calibrate the integral kernel's")
     args = ap.parse_args()
+    if args.calibrate_copy > 0:
+        calibrate_copy(args.calibrate_copy)
+        return
+    if args.only_headline:
+        args.secondary_steps = args.uneven_steps = args.mixed_steps = args.stream_steps = args.solid_steps = 0
+        args.no_cpu_baseline = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (quartets shard across GPUs "
               "with no communication; see the design notes). Run with --gpus 1.", file=sys.stderr)

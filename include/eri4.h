@@ -171,6 +171,31 @@ eri4_status eri4_batch_coulomb(int la, int lb, int lc, int ld, int64_t nquartets
                                const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
                                const double* dens, double* work, int64_t work_size, double* out, hipStream_t stream);
 
+/*
+ * Exchange-type contraction without forming (ab|cd): for each quartet of one
+ * class,
+ *   K_ac = sum_bd (ab|cd) D_bd
+ * (Sec. 3: Fock-matrix elements computed directly from the first transform's
+ * [ab|q] instead of from stored integrals; the paper leaves exchange to later
+ * work).  The density's d index goes to Hermite space per ket primitive pair
+ * and component b, F^b[q][c] = sum_d E_cd^q D_bd, and the first transform's
+ * [ab|q] is contracted with it on the matrix cores; the second transform
+ * (eq. (cd_to_hermite)) never runs.  FP64, Cartesian.
+ *   dens  device double [nquartets][Nb][Nd]  each quartet's density block D_bd
+ *   out   device double [nquartets][Na][Nc]  K contributions, quartets in input order
+ *   work  device double [work_size], caller-owned scratch (F^b and per-b partial rows)
+ * Other arguments as eri4_batch; quartets run in passes of as many as the
+ * workspace holds (eri4_exchange_work_size(la, lb, lc, ld, kmax, n) doubles
+ * for n quartets, -1 for bad arguments).  Each element of out is a sum over b
+ * in a fixed order (reproducible bits).  Symmetry partners (the other three
+ * exchange contractions of the quartet) are the caller's.
+ */
+int64_t eri4_exchange_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets);
+eri4_status eri4_batch_exchange(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                                const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                                const double* dens, double* work, int64_t work_size, double* out,
+                                hipStream_t stream);
+
 eri4_status eri4_solid_coefficients(int l, double* C);
 int64_t eri4_solid_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets);
 eri4_status eri4_batch_solid(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
@@ -305,6 +330,8 @@ eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, c
  *   out       device double, the blocks J_i[Na][Nb] one after the other in list
  *             order (eri4_plan_output_size doubles; eri4_plan_output_offsets
  *             gives the nbra block offsets)
+ * With an empty ket list (nket = 0) every J_i is an empty sum: execute only
+ * zeroes out (the list and work pointers are not read).
  * Other plan calls apply (destroy, output size and offsets); the other execute
  * calls reject a Coulomb plan.  Execute is enqueue-only and capturable, as
  * eri4_plan_execute.

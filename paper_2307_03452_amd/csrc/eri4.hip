@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <new>
@@ -31,6 +32,13 @@ void solid_dense(int l, double* C);
 
 __global__ void reset_counter_kernel(int* counter) {
   if (threadIdx.x == 0) counter[0] = 0;
+}
+
+// out[0..n) = 0 (a kernel rather than a memset, so that graph captures of the
+// calls that use it stay correct on replay)
+__global__ void zero_fill_kernel(double* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -138,7 +146,7 @@ struct DeviceState {
 };
 
 std::mutex g_mu;
-std::vector<DeviceState> g_dev;
+std::deque<DeviceState> g_dev;  // a deque: growing it keeps pointers to existing entries valid
 
 #define HIP_TRY(call)                                                                     \
   do {                                                                                    \
@@ -151,6 +159,7 @@ eri4_status set_attrs() {
   HIP_TRY(solid_set_attrs());
   HIP_TRY(plan_solid_set_attrs());
   HIP_TRY(coulomb_set_attrs());
+  HIP_TRY(exchange_set_attrs());
   HIP_TRY(plan_coulomb_set_attrs());
   HIP_TRY(plan_set_attrs_f64());
   HIP_TRY(plan_set_attrs_f32());
@@ -426,6 +435,34 @@ int64_t eri4_coulomb_work_size(int la, int lb, int lc, int ld, int kmax, int64_t
   return nquartets * kmax * kmax * ds;
 }
 
+// J for nquartets quartets in passes of as many as the workspace (work_size
+// doubles) holds the Hermite-space densities of: per pass, the density kernel,
+// then the integral kernel.  Arguments already checked; d is initialised.
+static eri4_status coulomb_passes(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                                  const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                                  const double* dens, double* work, int64_t work_size, double* out,
+                                  hipStream_t stream, const DeviceState* d) {
+  ClassParams p;
+  int64_t ds;
+  if (!coulomb_params(la, lb, lc, ld, kmax, d, &p, &ds))
+    return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
+  const int64_t perq = (int64_t)kmax * kmax * ds;
+  int64_t chunk = work_size / perq;
+  if (chunk < 1)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below one quartet's %lld",
+                (long long)work_size, (long long)perq);
+  chunk = std::min<int64_t>(chunk, std::min<int64_t>(((int64_t)1 << 30) / p.nrt, INT32_MAX));
+  for (int64_t q0 = 0; q0 < nquartets; q0 += chunk) {
+    const int64_t nq = std::min(chunk, nquartets - q0);
+    hipError_t e = coulomb_dket_launch(p, nq, stream, centers, exponents, coeffs, nprim, dens, work, q0, ds);
+    if (e == hipSuccess)
+      e = coulomb_launch(p, dim3((unsigned)(nq * p.nrt)), stream, Tables{d->boys, d->rtab}, centers, exponents,
+                         coeffs, nprim, out, q0, work, ds);
+    if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
+  }
+  return ERI4_SUCCESS;
+}
+
 eri4_status eri4_batch_coulomb(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
                                const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
                                const double* dens, double* work, int64_t work_size, double* out, hipStream_t stream) {
@@ -439,7 +476,53 @@ eri4_status eri4_batch_coulomb(int la, int lb, int lc, int ld, int64_t nquartets
   int64_t ds;
   if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds))
     return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
-  const int64_t perq = (int64_t)kmax * kmax * ds;
+  if (work_size < (int64_t)kmax * kmax * ds)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below one quartet's %lld",
+                (long long)work_size, (long long)kmax * kmax * ds);
+  DeviceState* d;
+  st = ensure_device(&d);
+  if (st != ERI4_SUCCESS) return st;
+  return coulomb_passes(la, lb, lc, ld, nquartets, centers, exponents, coeffs, nprim, kmax, dens, work, work_size,
+                        out, stream, d);
+}
+
+// Exchange contraction: the library's tile for the class, with the bra rows
+// ordered (b, a) and a padded to whole 16-row blocks (one b per block); fbs
+// doubles of F^b per ket primitive pair and b, ps doubles of partial rows
+// y^b per quartet.
+static bool exchange_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* p,
+                            int64_t* fbs, int64_t* ps) {
+  if (!pick_params(la, lb, lc, ld, kmax, d, kMaxLdsBytes, p)) return false;
+  const int blocks = p->nb * ((p->na + 15) / 16);
+  p->nrt = (blocks + p->rb - 1) / p->rb;
+  *fbs = (int64_t)((p->nc + 15) / 16) * 16 * p->nq4;
+  *ps = (int64_t)p->nb * p->na * p->nc;
+  return true;
+}
+
+int64_t eri4_exchange_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets) {
+  if (check_class(la, lb, lc, ld, nquartets, kmax) != ERI4_SUCCESS) return -1;
+  ClassParams p;
+  int64_t fbs, ps;
+  if (!exchange_params(la, lb, lc, ld, kmax, nullptr, &p, &fbs, &ps)) return -1;
+  return nquartets * ((int64_t)kmax * kmax * p.nb * fbs + ps);
+}
+
+eri4_status eri4_batch_exchange(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                                const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                                const double* dens, double* work, int64_t work_size, double* out,
+                                hipStream_t stream) {
+  g_err.clear();
+  eri4_status st = check_class(la, lb, lc, ld, nquartets, kmax);
+  if (st != ERI4_SUCCESS) return st;
+  if (nquartets == 0) return ERI4_SUCCESS;
+  if (!centers || !exponents || !coeffs || !nprim || !dens || !out || !work)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  ClassParams p;
+  int64_t fbs, ps;
+  if (!exchange_params(la, lb, lc, ld, kmax, nullptr, &p, &fbs, &ps))
+    return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
+  const int64_t perq = (int64_t)kmax * kmax * p.nb * fbs + ps;
   int64_t chunk = work_size / perq;
   if (chunk < 1)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below one quartet's %lld",
@@ -447,14 +530,14 @@ eri4_status eri4_batch_coulomb(int la, int lb, int lc, int ld, int64_t nquartets
   DeviceState* d;
   st = ensure_device(&d);
   if (st != ERI4_SUCCESS) return st;
-  (void)coulomb_params(la, lb, lc, ld, kmax, d, &p, &ds);
+  (void)exchange_params(la, lb, lc, ld, kmax, d, &p, &fbs, &ps);
   chunk = std::min<int64_t>(chunk, std::min<int64_t>(((int64_t)1 << 30) / p.nrt, INT32_MAX));
   for (int64_t q0 = 0; q0 < nquartets; q0 += chunk) {
     const int64_t nq = std::min(chunk, nquartets - q0);
-    hipError_t e = coulomb_dket_launch(p, nq, stream, centers, exponents, coeffs, nprim, dens, work, q0, ds);
-    if (e == hipSuccess)
-      e = coulomb_launch(p, dim3((unsigned)(nq * p.nrt)), stream, Tables{d->boys, d->rtab}, centers, exponents,
-                         coeffs, nprim, out, q0, work, ds);
+    double* fb = work;
+    double* part = work + nq * (int64_t)kmax * kmax * p.nb * fbs;
+    const hipError_t e = exchange_launch(p, nq, stream, Tables{d->boys, d->rtab}, centers, exponents, coeffs, nprim,
+                                         dens, fb, fbs, part, out, q0);
     if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
   }
   return ERI4_SUCCESS;
@@ -901,7 +984,15 @@ eri4_status eri4_plan_execute_coulomb(eri4_plan plan, const double* bra_centers,
   g_err.clear();
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
   if (!plan->coul) return fail(ERI4_ERROR_INVALID_ARGUMENT, "not a Coulomb plan (eri4_plan_create_coulomb)");
-  if (plan->nitems == 0) return ERI4_SUCCESS;
+  if (plan->nitems == 0) {
+    // an empty ket list: every J_i is an empty sum
+    if (plan->out_size == 0) return ERI4_SUCCESS;
+    if (!out) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+    const int64_t nb = std::min<int64_t>((plan->out_size + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_fill_kernel, dim3((unsigned)nb), dim3(256), 0, stream, out, plan->out_size);
+    HIP_TRY(hipGetLastError());
+    return ERI4_SUCCESS;
+  }
   if (!bra_centers || !bra_exponents || !bra_coeffs || !ket_centers || !ket_exponents || !ket_coeffs || !ket_dens ||
       !out)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");

@@ -72,6 +72,44 @@ __device__ __forceinline__ typename Acc<F32>::type acc_zero() {
   return typename Acc<F32>::type{0, 0, 0, 0};
 }
 
+// Stage timers (compile-time, ERI4_STAGE_TIMERS): wave 0 of each workgroup of
+// the Cartesian kernels reads the shader clock after every barrier that ends a
+// stage and adds the cycles since the previous read to that stage; the sums of
+// all workgroups go to g_stage_cycles at the end of each tile.  The stages
+// follow the paper's per-kernel breakdown (Table 2): pair data, Boys function
+// and bra 1-d tables ([0]^(m) of eq. (boys)), the recursion of eq. (md1), the
+// first transform (eq. (ab_to_hermite)), the tile move and ket tables, and
+// the second transform with the output write (eq. (cd_to_hermite)).
+enum { kStPair = 0, kStBoysE, kStR, kStGemm1, kStMove, kStGemm2, kStTiles, kStCount };
+#ifdef ERI4_STAGE_TIMERS
+__device__ unsigned long long g_stage_cycles[kStCount];
+struct StageClock {
+  unsigned long long t, acc[kStCount];
+  __device__ __forceinline__ void start() {
+    t = __builtin_readcyclecounter();
+    for (int i = 0; i < kStCount; ++i) acc[i] = 0;
+  }
+  __device__ __forceinline__ void mark(int st) {
+    const unsigned long long n = __builtin_readcyclecounter();
+    acc[st] += n - t;
+    t = n;
+  }
+  __device__ __forceinline__ void flush(int tid) {
+    if (tid == 0) {
+      acc[kStTiles] = 1;
+      for (int i = 0; i < kStCount; ++i) atomicAdd(&g_stage_cycles[i], acc[i]);
+    }
+  }
+};
+#define ERI4_STAGE(st) clk.mark(st)
+#else
+struct StageClock {
+  __device__ __forceinline__ void start() {}
+  __device__ __forceinline__ void flush(int) {}
+};
+#define ERI4_STAGE(st) ((void)0)
+#endif
+
 // F_m(T), eq. (boys): Taylor expansion on the grid below kBoysTMax, asymptotic
 // form above.  Negative T gives NaN.
 __device__ double boys_fm(int m, double T, const double* __restrict__ tab) {
@@ -542,6 +580,76 @@ __device__ __forceinline__ void gemm2_group_h(const ClassParams& cp, const doubl
     }
 }
 
+// Exchange mode: bra row order.  Padded row pr of a quartet is shell-b
+// component pr / P and shell-a component pr % P, with P = 16 * ceil(na / 16)
+// rows per b (components a >= na are padding).
+__device__ __forceinline__ int exch_rows_per_b(const ClassParams& cp) { return 16 * ((cp.na + 15) / 16); }
+__device__ __forceinline__ void exch_row(const ClassParams& cp, int pr, int& ia, int& ib) {
+  const int P = exch_rows_per_b(cp);
+  ib = pr / P;
+  ia = pr - ib * P;
+}
+
+// y blocks of one ket pair: block i of this wave (blk = wave + 8 i) is row
+// block r = blk / ncc and column block cc = blk % ncc (c = 16 cc + lane % 16):
+//   y[r][cc] += sum_q X[row block r][q] F^b[q][cc],  b the row block's shell-b component.
+// F^b of this ket pair at F + (b * ncc + cc) * nq4 * 16 in operand order (k
+// step s, lane l: F^b[4 s + l / 16][16 cc + l % 16]).  The operands of eight k
+// steps are read before their products are issued.
+template <int NR>
+__device__ __forceinline__ void exch_gemm(const ClassParams& cp, const double* __restrict__ X,
+                                          const double* __restrict__ F, int row0, int wave, int lane, d4 (&yacc)[2]) {
+  const int g = lane >> 4, n = lane & 15;
+  const int ncc = (cp.nc + 15) / 16;
+  const int P = exch_rows_per_b(cp);
+  const int64_t fs = (int64_t)cp.nq4 * 16;
+  const int nq4 = cp.nq4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int blk = wave + 8 * i;
+    if (blk >= NR * ncc) break;
+    const int r = blk / ncc, cc = blk - (blk / ncc) * ncc;
+    const int ib = (row0 + r * 16) / P;  // one b per row block
+    if (ib >= cp.nb) continue;           // padding rows past the last b
+    const double* __restrict__ Fb = F + ((int64_t)ib * ncc + cc) * fs + lane;
+    const double* __restrict__ Xr = X + (r * 16 + n) * cp.xs + g;
+    d4 acc = yacc[i];
+    int kk = 0;
+    for (; kk + 32 <= nq4; kk += 32) {
+      double a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[u] = Fb[(kk + 4 * u) * 16];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = Xr[kk + 4 * u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = mfma16<false>(a[u], b[u], acc);
+    }
+    for (; kk < nq4; kk += 4) acc = mfma16<false>(Xr[kk], Fb[kk * 16], acc);
+    yacc[i] = acc;
+  }
+}
+
+// y of this wave's blocks to outq[(b * na + a) * nc + c] (valid a, b, c only).
+template <int NR>
+__device__ __forceinline__ void exch_store(const ClassParams& cp, const d4 (&yacc)[2], double* __restrict__ outq,
+                                           int row0, int wave, int lane) {
+  const int g = lane >> 4, n = lane & 15;
+  const int ncc = (cp.nc + 15) / 16;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int blk = wave + 8 * i;
+    if (blk >= NR * ncc) break;
+    const int r = blk / ncc, cc = blk - (blk / ncc) * ncc;
+    const int ic = 16 * cc + n;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      int ia, ib;
+      exch_row(cp, row0 + r * 16 + acc_row<false>(jj, g), ia, ib);
+      if (ia < cp.na && ib < cp.nb && ic < cp.nc) outq[((int64_t)ib * cp.na + ia) * cp.nc + ic] = yacc[i][jj];
+    }
+  }
+}
+
 // LDS regions of the fused kernel (see make_params for the layout).
 struct Lds {
   double *sh, *baseM, *kpair, *bpair, *pqv, *box, *box1, *brae, *X, *kete;
@@ -589,7 +697,13 @@ __device__ __forceinline__ void ket_scale(const Lds& s, int kmax, int Ka, int Kb
 // the ket density in Hermite space, dket[q] = sum_cd E_cd^q D_cd of ket pair
 // (k, l) at hk + (k * kmax + l) * hks (coulomb_dket_kernel), giving
 // J_ab = sum_cd (ab|cd) D_cd, written to outq[ab] (FP64, Cartesian).
-template <int NR, int NC1, int LAY, bool F32, bool SOLID = false, bool COUL = false>
+// EXCH: no second transform either; bra rows are ordered (b, a) with a padded
+// to a multiple of 16 (exch_row), so each 16-row block has one b, and [ab|q]
+// is contracted on the matrix cores with F^b[q][c] = sum_d E_cd^q D_bd of ket
+// pair (k, l) (exchange_f_kernel, at hk + (k * kmax + l) * hks in operand
+// order), accumulated over the ket pairs into y[a][c] = sum_d (ab|cd) D_bd,
+// written to outq[(b * na + a) * nc + c] for the tile's b (FP64, Cartesian).
+template <int NR, int NC1, int LAY, bool F32, bool SOLID = false, bool COUL = false, bool EXCH = false>
 __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, const double* __restrict__ boys_tab,
                            const uint2 (&rent)[LAY == kLaySlab ? kRPerThread : kRPerBox], double* __restrict__ outq,
                            int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane,
@@ -597,6 +711,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
                            int64_t hbs = 0, int64_t hks = 0, double* jt = nullptr) {
   static_assert(!(SOLID && F32), "solid-harmonic output runs FP64 transforms");
   static_assert(!(COUL && (F32 || SOLID)), "the Coulomb contraction runs FP64 Cartesian transforms");
+  static_assert(!(EXCH && (F32 || SOLID || COUL)), "the exchange contraction runs FP64 Cartesian transforms");
   if constexpr (COUL) {
     // J rows of the tile in jt[0..63], each wave's partial rows in
     // jt[64 + 64 * wave ..] (kCoulLds doubles of the kernel's LDS)
@@ -616,9 +731,18 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
   int rowx[NR], rowy[NR], rowz[NR];
 #pragma unroll
   for (int r = 0; r < NR && !SOLID; ++r) {
-    const int ab = row0 + r * 16 + (lane & 15);
-    if (ab < cp.nab) {
-      const int ia = ab / cp.nb, ib = ab - ia * cp.nb;
+    int ia, ib;
+    bool valid;
+    if constexpr (EXCH) {
+      exch_row(cp, row0 + r * 16 + (lane & 15), ia, ib);
+      valid = ia < cp.na && ib < cp.nb;
+    } else {
+      const int ab = row0 + r * 16 + (lane & 15);
+      valid = ab < cp.nab;
+      ia = ab / cp.nb;
+      ib = ab - ia * cp.nb;
+    }
+    if (valid) {
       int ax, ay, az, bx, by, bz;
       cart_of(cp.la, ia, ax, ay, az);
       cart_of(cp.lb, ib, bx, by, bz);
@@ -643,6 +767,10 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
   const int ncbw = (wave < cp.ncdb) ? (cp.ncdb - wave + 7) / 8 : 0;  // output column blocks of this wave
 
   const double pref = 2.0 * pow(M_PI, 2.5);
+  StageClock clk;
+  clk.start();
+  // EXCH: y blocks (row block, 16 columns c) of this wave, kept over the ket pairs
+  d4 yacc[2] = {acc_zero<false>(), acc_zero<false>()};
 
   for (int kl = 0; kl < Kc * Kd; ++kl) {
     if (tid == 0) {
@@ -662,6 +790,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
         make_pair(s.bpair, ex[i], ex[kmax + j], co[i], co[kmax + j], A, B);
       }
       __syncthreads();
+      ERI4_STAGE(kStPair);
       if (wave == 0) {
         if (lane < 3) s.pqv[lane] = s.bpair[2 + lane] - s.kpair[2 + lane];
         if (lane <= cp.L) {
@@ -685,10 +814,12 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
                      lane);
       }
       __syncthreads();
+      ERI4_STAGE(kStBoysE);
       if constexpr (LAY == kLayBox2)
         hermite_r_lds2(s.box, s.box1, s.baseM, cp.L, s.pqv, rent, tid);
       else
         hermite_r_lds(s.box, s.baseM, cp.L, s.pqv, rent, tid);
+      ERI4_STAGE(kStR);
       // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
       if constexpr (NC1 > 0 && SOLID) {
         const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
@@ -698,6 +829,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
         gemm1_pair<NR, NC1, SLAB, F32>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, tq, cp.np4, cp.L, cp.S1, lane);
       }
       __syncthreads();
+      ERI4_STAGE(kStGemm1);
     }
 
     if constexpr (COUL) {
@@ -750,11 +882,21 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
             s.X[(r * 16 + acc_row<F32>(jj, lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = acc1[r][c][jj];
         }
     }
+    if constexpr (EXCH) {
+      // y[a][c] += sum_q [ab|q] F^b[q][c] for this ket pair; the barrier after
+      // it protects the tile (aliased by the next pair's R box) until all reads
+      __syncthreads();
+      const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
+      exch_gemm<NR>(cp, s.X, hk + (k * kmax + l) * hks, row0, wave, lane, yacc);
+      __syncthreads();
+      continue;
+    }
     if constexpr (!SOLID) {
       if (wave == 0)
         build_etab(s.kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / s.kpair[0], s.kpair + 5, s.kpair + 8, true, lane);
     }
     __syncthreads();
+    ERI4_STAGE(kStMove);
 
     // second transform, written to HBM (accumulated over kl); groups of
     // kGroup column blocks (2 with four row blocks, for the accumulators)
@@ -790,11 +932,14 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       }
     }
     __syncthreads();
+    ERI4_STAGE(kStGemm2);
   }
+  clk.flush(tid);
   if constexpr (COUL) {
     __syncthreads();
     if (tid < NR * 16 && row0 + tid < cp.nab) outq[row0 + tid] = jt[tid];
   }
+  if constexpr (EXCH) exch_store<NR>(cp, yacc, outq, row0, wave, lane);
 }
 
 // All the work of one tile: quartet q, bra rows rt*RB*16.., whose integrals
@@ -804,7 +949,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
 // pairs (PAIRS true: bra pair q / nket, ket pair q % nket, each list centers
 // [i][2][3], exps/coefs [i][2][kmax]; centers/exps/coefs are the bra list).
 // SOLID: solid-harmonic rows and columns, H matrices from hb / hk (fused_body).
-template <int RB, int LAY, bool F32, bool PAIRS, bool SOLID = false, bool COUL = false>
+template <int RB, int LAY, bool F32, bool PAIRS, bool SOLID = false, bool COUL = false, bool EXCH = false>
 __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned char* lds,
                                              const double* __restrict__ boys_tab,
                                              const uint2* __restrict__ rtab_L,
@@ -869,18 +1014,28 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
   const int Ka = shn[0], Kb = shn[1], Kc = shn[2], Kd = shn[3];
   const int row0 = rt * RB * 16;
   if (Ka < 1 || Ka > kmax || Kb < 1 || Kb > kmax || Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax) {
-    const int nrows = min(RB * 16, cp.nab - row0);
-    const int ncols = COUL ? 1 : cp.ncd;
-    double* o = outq + (int64_t)row0 * ncols;
-    for (int i = tid; i < nrows * ncols; i += kThreads) o[i] = __builtin_nan("");
+    if constexpr (EXCH) {
+      // this tile's rows (b, a) of y
+      for (int i = tid; i < RB * 16 * cp.nc; i += kThreads) {
+        int ia, ib;
+        exch_row(cp, row0 + i / cp.nc, ia, ib);
+        if (ia < cp.na && ib < cp.nb) outq[((int64_t)ib * cp.na + ia) * cp.nc + i % cp.nc] = __builtin_nan("");
+      }
+    } else {
+      const int nrows = min(RB * 16, cp.nab - row0);
+      const int ncols = COUL ? 1 : cp.ncd;
+      double* o = outq + (int64_t)row0 * ncols;
+      for (int i = tid; i < nrows * ncols; i += kThreads) o[i] = __builtin_nan("");
+    }
     __syncthreads();
     return;
   }
   const int nc1 = (wave < cp.nqb) ? min(kMaxC1, (cp.nqb - wave + 7) / 8) : 0;  // [ab|q] column blocks of this wave
-  const int nrv = min(RB, (cp.nab - row0 + 15) / 16);                             // valid row blocks of this tile
+  const int nrows_all = EXCH ? cp.nb * 16 * ((cp.na + 15) / 16) : cp.nab;           // (padded) bra rows
+  const int nrv = min(RB, (nrows_all - row0 + 15) / 16);                          // valid row blocks of this tile
 #define BODY(NR, NC1) \
-  fused_body<NR, NC1, LAY, F32, SOLID, COUL>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane, hb, hk, \
-                                             hbs, hks, jt)
+  fused_body<NR, NC1, LAY, F32, SOLID, COUL, EXCH>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane, \
+                                                   hb, hk, hbs, hks, jt)
   constexpr int NR2 = RB >= 2 ? 2 : 1;
   if constexpr (RB == 4) {
     // 64-row tiles (kets with at most 2 column blocks per wave): the last tile

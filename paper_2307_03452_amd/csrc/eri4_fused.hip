@@ -45,4 +45,19 @@ hipError_t fused_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Ta
   }
 }
 
+#ifdef ERI4_STAGE_TIMERS
+// Stage-timer build only: the per-stage cycle sums of the Cartesian fused
+// kernels (kStCount counters in the order of the stage enum; the last one
+// counts tiles), then zeroed if reset.  Returns 0, or 4 on a HIP error.
+extern "C" int eri4_stage_cycles(unsigned long long* out, int reset) {
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_stage_cycles), sizeof(unsigned long long) * kStCount);
+  if (e == hipSuccess && reset) {
+    const unsigned long long z[kStCount] = {0};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_stage_cycles), z, sizeof z);
+  }
+  return e == hipSuccess ? 0 : 4;
+}
+#endif
+
 }  // namespace eri4

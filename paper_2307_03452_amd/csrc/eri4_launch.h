@@ -1,6 +1,7 @@
 // eri4_launch.h -- host-side entry points to the kernels of liberi4 that are
 // compiled in their own translation units (eri4_fused.hip, eri4_solid.hip,
-// eri4_coulomb.hip and the four eri4_plan*.hip).  Not part of the public ABI.
+// eri4_coulomb.hip, eri4_exchange.hip and the four eri4_plan*.hip).  Not part
+// of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -42,6 +43,15 @@ hipError_t coulomb_dket_launch(const ClassParams& p, int64_t nq, hipStream_t s, 
 hipError_t coulomb_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
                           const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0,
                           const double* dket, int64_t ds);
+
+// Exchange contraction (eri4_exchange.hip): F^b of every ket primitive pair
+// and shell-b component of quartets q0..q0+nq-1 (fbs doubles each), the
+// integral kernels writing the partial rows y^b into part, and the sum over b
+// into out (K [q][Na][Nc]).
+hipError_t exchange_set_attrs();
+hipError_t exchange_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
+                           const double* exps, const double* coefs, const int32_t* nprim, const double* dens,
+                           double* fb, int64_t fbs, double* part, double* out, int64_t q0);
 
 // Where the shells of quartet q come from: per-quartet arrays (nket == 0:
 // centers [q][4][3], exps/coefs [q][4][kmax]), or a bra and a ket list of

@@ -11,7 +11,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liberi4.so")
+# ERI4_LIBRARY may name another build of the same library (the stage-timer
+# variant, liberi4_stages.so); the default is the in-tree liberi4.so
+LIB_PATH = os.environ.get("ERI4_LIBRARY") or os.path.join(HERE, "liberi4.so")
 
 ERI4_MAX_L = 7
 ERI4_MAX_K = 16
@@ -52,7 +54,8 @@ EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version",
            "eri4_plan_execute", "eri4_plan_destroy", "eri4_plan_create_pairs", "eri4_plan_execute_pairs", "eri4_plan_work_size",
            "eri4_plan_create_coulomb", "eri4_plan_execute_coulomb",
            "eri4_boys", "eri4_hermite_r", "eri4_hermite_e", "eri4_solid_coefficients", "eri4_solid_work_size",
-           "eri4_batch_solid", "eri4_coulomb_work_size", "eri4_batch_coulomb")
+           "eri4_batch_solid", "eri4_coulomb_work_size", "eri4_batch_coulomb", "eri4_exchange_work_size",
+           "eri4_batch_exchange")
 
 _lib = None
 
@@ -91,6 +94,10 @@ def lib() -> ctypes.CDLL:
         L.eri4_coulomb_work_size.restype = i64
         L.eri4_batch_coulomb.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp, i64, vp, vp]
         L.eri4_batch_coulomb.restype = c_int
+        L.eri4_exchange_work_size.argtypes = [c_int] * 5 + [i64]
+        L.eri4_exchange_work_size.restype = i64
+        L.eri4_batch_exchange.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp, i64, vp, vp]
+        L.eri4_batch_exchange.restype = c_int
         L.eri4_plan_create.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int]
         L.eri4_plan_create.restype = c_int
         L.eri4_plan_create_tuned.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int, vp, c_int]
@@ -150,6 +157,25 @@ def _ptr(t, dtype_name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check_shells(centers, exps, coefs, nprim=None):
+    """Shapes of per-quartet shell arrays: centers [nq,4,3], exps/coefs
+    [nq,4,kmax], nprim [nq,4]; returns (nq, kmax)."""
+    nq = centers.shape[0]
+    if tuple(centers.shape) != (nq, 4, 3) or exps.dim() != 3 or tuple(exps.shape[:2]) != (nq, 4):
+        raise ValueError("centers must be [nq,4,3] and exps [nq,4,kmax]")
+    kmax = exps.shape[2]
+    if tuple(coefs.shape) != (nq, 4, kmax):
+        raise ValueError("coefs must have the shape of exps")
+    if nprim is not None and tuple(nprim.shape) != (nq, 4):
+        raise ValueError("nprim must be [nq,4]")
+    return nq, kmax
+
+
+def _check_out(t, n, what="output"):
+    if t.numel() < n:
+        raise ValueError(f"{what} buffer holds {t.numel()} doubles, {n} needed")
+
+
 def ncart(l: int) -> int:
     return lib().eri4_ncart(int(l))
 
@@ -174,11 +200,11 @@ def batch(ls, centers, exps, coefs, nprim, out=None, stream=None):
     """
     import torch
     la, lb, lc, ld = (int(x) for x in ls)
-    nq = centers.shape[0]
-    kmax = exps.shape[2]
+    nq, kmax = _check_shells(centers, exps, coefs, nprim)
     if out is None:
         out = torch.empty((nq, ncart(la), ncart(lb), ncart(lc), ncart(ld)), dtype=torch.float64,
                           device=centers.device)
+    _check_out(out, nq * ncart(la) * ncart(lb) * ncart(lc) * ncart(ld))
     _check(lib().eri4_batch(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
                             _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(out, "float64"),
                             _stream(stream)))
@@ -212,11 +238,11 @@ def batch_solid(ls, centers, exps, coefs, nprim, work=None, out=None, stream=Non
     matrices (default: enough for one pass over all quartets)."""
     import torch
     la, lb, lc, ld = (int(x) for x in ls)
-    nq = centers.shape[0]
-    kmax = exps.shape[2]
+    nq, kmax = _check_shells(centers, exps, coefs, nprim)
     if out is None:
         out = torch.empty((nq, nsolid(la), nsolid(lb), nsolid(lc), nsolid(ld)), dtype=torch.float64,
                           device=centers.device)
+    _check_out(out, nq * nsolid(la) * nsolid(lb) * nsolid(lc) * nsolid(ld))
     if work is None:
         work = torch.empty(max(1, solid_work_size(ls, kmax, nq)), dtype=torch.float64, device=centers.device)
     _check(lib().eri4_batch_solid(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
@@ -239,15 +265,43 @@ def batch_coulomb(ls, centers, exps, coefs, nprim, dens, work=None, out=None, st
     [nq, Na, Nb]."""
     import torch
     la, lb, lc, ld = (int(x) for x in ls)
-    nq = centers.shape[0]
-    kmax = exps.shape[2]
+    nq, kmax = _check_shells(centers, exps, coefs, nprim)
     if out is None:
         out = torch.empty((nq, ncart(la), ncart(lb)), dtype=torch.float64, device=centers.device)
+    _check_out(out, nq * ncart(la) * ncart(lb))
+    _check_out(dens, nq * ncart(lc) * ncart(ld), "density")
     if work is None:
         work = torch.empty(max(1, coulomb_work_size(ls, kmax, nq)), dtype=torch.float64, device=centers.device)
     _check(lib().eri4_batch_coulomb(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
                                     _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(dens, "float64"),
                                     _ptr(work, "float64"), work.numel(), _ptr(out, "float64"), _stream(stream)))
+    return out
+
+
+def exchange_work_size(ls, kmax: int, nq: int) -> int:
+    """Doubles of workspace eri4_batch_exchange needs to run nq quartets in one pass."""
+    n = lib().eri4_exchange_work_size(*(int(x) for x in ls), int(kmax), int(nq))
+    if n < 0:
+        raise ValueError("bad class or sizes")
+    return n
+
+
+def batch_exchange(ls, centers, exps, coefs, nprim, dens, work=None, out=None, stream=None):
+    """K_ac = sum_bd (ab|cd) D_bd for every quartet of one class, without
+    forming (ab|cd): dens float64 [nq, Nb, Nd] (device), returns float64
+    [nq, Na, Nc]."""
+    import torch
+    la, lb, lc, ld = (int(x) for x in ls)
+    nq, kmax = _check_shells(centers, exps, coefs, nprim)
+    if out is None:
+        out = torch.empty((nq, ncart(la), ncart(lc)), dtype=torch.float64, device=centers.device)
+    _check_out(out, nq * ncart(la) * ncart(lc))
+    _check_out(dens, nq * ncart(lb) * ncart(ld), "density")
+    if work is None:
+        work = torch.empty(max(1, exchange_work_size(ls, kmax, nq)), dtype=torch.float64, device=centers.device)
+    _check(lib().eri4_batch_exchange(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
+                                     _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(dens, "float64"),
+                                     _ptr(work, "float64"), work.numel(), _ptr(out, "float64"), _stream(stream)))
     return out
 
 
@@ -408,6 +462,7 @@ class CoulombPlan(Plan):
         self.nbra, self.nket = bl.shape[0], kl.shape[0]
         self.nq = self.nbra * self.nket
         self.kmax = int(kmax)
+        self.ket_dens_size = int(sum(ncart(int(a)) * ncart(int(b)) for a, b in kl))
         h = ctypes.c_void_p()
         vp = ctypes.c_void_p
         _check(lib().eri4_plan_create_coulomb(ctypes.byref(h), self.nbra, bl.ctypes.data_as(vp), bn.ctypes.data_as(vp),
@@ -431,6 +486,11 @@ class CoulombPlan(Plan):
             out = torch.empty(max(1, self.output_size), dtype=torch.float64, device=bra_centers.device)
         if work is None:
             work = torch.empty(max(1, self.work_size), dtype=torch.float64, device=bra_centers.device)
+        _check_out(out, self.output_size)
+        _check_out(ket_dens, self.ket_dens_size, "ket density")
+        for c, e, w, n in ((bra_centers, bra_exps, bra_coefs, self.nbra), (ket_centers, ket_exps, ket_coefs, self.nket)):
+            if tuple(c.shape) != (n, 2, 3) or tuple(e.shape) != (n, 2, self.kmax) or tuple(w.shape) != (n, 2, self.kmax):
+                raise ValueError("pair lists do not match the plan")
         _check(lib().eri4_plan_execute_coulomb(
             self._h, _ptr(bra_centers, "float64"), _ptr(bra_exps, "float64"), _ptr(bra_coefs, "float64"),
             _ptr(ket_centers, "float64"), _ptr(ket_exps, "float64"), _ptr(ket_coefs, "float64"),

@@ -250,3 +250,12 @@ def ket_densities(b: Batch, seed: int, ls=None) -> np.ndarray:
     ls = b.ls if ls is None else ls
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-1.0, 1.0, size=(b.nq, ncart(ls[2]), ncart(ls[3])))
+
+
+def exchange_densities(b: Batch, seed: int, ls=None) -> np.ndarray:
+    """A density block D[q][Nb][Nd] per quartet (uniform in [-1, 1]) for the
+    exchange contraction K_ac = sum_bd (ab|cd) D_bd; ls defaults to the
+    batch's class."""
+    ls = b.ls if ls is None else ls
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-1.0, 1.0, size=(b.nq, ncart(ls[1]), ncart(ls[3])))

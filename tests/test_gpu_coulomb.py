@@ -144,6 +144,43 @@ def test_coulomb_pair_plan_rejects_other_executes_and_small_workspaces(torch):
     assert b"Coulomb" in L.eri4_last_error()
 
 
+def test_coulomb_pair_plan_with_an_empty_ket_list_gives_zeros(torch):
+    """J_i over an empty ket list is an empty sum: execute zeroes the output
+    (which starts as garbage here) instead of leaving it untouched."""
+    bra = inputs.pair_list(3, 67, kmax=2)
+    z = lambda *shape: torch.zeros(*shape, dtype=torch.float64, device="cuda")
+    p = eri4.CoulombPlan(bra.l, bra.nprim, np.zeros((0, 2), np.int32), np.zeros((0, 2), np.int32), 2)
+    assert p.output_size == sum(inputs.ncart(int(a)) * inputs.ncart(int(b)) for a, b in bra.l)
+    out = torch.full((p.output_size,), float("nan"), dtype=torch.float64, device="cuda")
+    d = lambda a: dev(torch, a)
+    p.execute(d(bra.centers), d(bra.exps), d(bra.coefs), z(0, 2, 3), z(0, 2, 2), z(0, 2, 2), z(1), out=out)
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == 0.0).all()
+
+
+def test_coulomb_wrappers_reject_short_buffers_and_bad_shapes(torch):
+    b = inputs.class_batch((4, 4, 4, 4), 2, 1, seed=68)
+    d = lambda a: dev(torch, a)
+    C, E, Co, N = d(b.centers), d(b.exps), d(b.coefs), d(b.nprim)
+    D = d(inputs.ket_densities(b, seed=69))
+    with pytest.raises(ValueError, match="density"):
+        eri4.batch_coulomb(b.ls, C, E, Co, N, D[:1].contiguous())
+    with pytest.raises(ValueError, match="output"):
+        eri4.batch_coulomb(b.ls, C, E, Co, N, D, out=torch.empty(10, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError, match="nprim"):
+        eri4.batch_coulomb(b.ls, C, E, Co, N[:1].contiguous(), D)
+    bra, ket = inputs.pair_list(2, 70, kmax=1), inputs.pair_list(2, 71, kmax=1)
+    p = eri4.CoulombPlan(bra.l, bra.nprim, ket.l, ket.nprim, 1)
+    args = (d(bra.centers), d(bra.exps), d(bra.coefs), d(ket.centers), d(ket.exps), d(ket.coefs))
+    with pytest.raises(ValueError, match="ket density"):
+        p.execute(*args, torch.zeros(3, dtype=torch.float64, device="cuda"))
+    kd = torch.zeros(p.ket_dens_size, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError, match="output"):
+        p.execute(*args, kd, out=torch.zeros(p.output_size - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError, match="pair lists"):
+        p.execute(args[0][:1].contiguous(), *args[1:], kd)
+
+
 def test_solid_batch_and_coulomb_plan_replay_in_a_hip_graph(torch):
     """eri4_batch_solid and a Coulomb pair-list plan captured in one HIP graph
     (no allocation, no memset nodes) give the eager results on every replay,

@@ -1,0 +1,165 @@
+"""Parity with the oracle on the benchmark workloads themselves, at their full
+sizes and in the launch configurations that bench.py times.
+
+- (ii|ii), K = 1, 512 quartets (seed 1002): every quartet, element by element.
+- (ii|ii), K = 5 per shell (K_bra = K_ket = 25), 512 quartets (seed 1003): the
+  whole batch on the GPU, 16 quartets against the oracle (each takes the
+  oracle about a minute of one core).
+- (kk|kk) and (ik|ik), K = 3 per shell, 256 quartets each: the FP64 plan
+  kernel over each batch, 2 quartets of each against the oracle.
+- The uneven 20 000-quartet batch (classes in {4,5,6}^4, K in 1..8 per shell,
+  seed 1004) through the FP64 plan kernel with the autotuned tiles: a
+  stratified sample of the five most common classes, two quartets per bucket
+  of K_a K_b K_c K_d, including each bucket's largest.
+
+Tolerance: per quartet, max |gpu - oracle| <= 1e-12 max |oracle| (Sec. 2's
+transforms in FP64; the reading of the tolerance is the same as for every
+other FP64 parity test).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03452_amd import eri4, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+ZERO_SCALE = 1e-250
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a ROCm device"
+    eri4.init()
+    return _t
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_batch(torch, b):
+    out = eri4.batch(b.ls, dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs),
+                     dev(torch, b.nprim))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_close(g, o, label):
+    scale = max(np.abs(o).max(), ZERO_SCALE)
+    assert np.isfinite(g).all(), label
+    err = np.abs(g - o).max()
+    assert err <= TOL * scale, (label, err, scale, err / scale)
+
+
+def oracle_of(b, idx):
+    """Oracle integrals of quartets idx of a mixed-class batch, by quartet."""
+    res, by_cls = {}, {}
+    for q in idx:
+        by_cls.setdefault(tuple(int(x) for x in b.lq[q]), []).append(int(q))
+    for ls, qs in by_cls.items():
+        s = inputs.subset(b, qs)
+        o = oracle.eri_md4(ls, s.centers, s.exps, s.coefs, s.nprim)
+        for i, q in enumerate(qs):
+            res[q] = o[i]
+    return res
+
+
+def check_plan(g_flat, offsets, b, idx):
+    o = oracle_of(b, idx)
+    for q in idx:
+        ref = o[int(q)]
+        g = g_flat[offsets[q]:offsets[q] + ref.size].reshape(ref.shape)
+        assert_close(g, ref, (int(q), tuple(int(x) for x in b.lq[q]), tuple(int(x) for x in b.nprim[q])))
+
+
+def test_iiii_k1_every_quartet(torch):
+    b = inputs.iiii(K=1)
+    assert (b.nq, b.kmax) == (512, 1)
+    g = run_batch(torch, b)
+    o = oracle.eri_md4(b.ls, b.centers, b.exps, b.coefs, b.nprim)
+    for q in range(b.nq):
+        assert_close(g[q], o[q], ("iiii K1", q))
+
+
+@pytest.mark.timeout(600)
+def test_iiii_k5_full_batch_16_quartets(torch):
+    b = inputs.iiii(K=5)
+    assert (b.nq, b.kmax) == (512, 5) and (b.nprim == 5).all()
+    g = run_batch(torch, b)
+    assert np.isfinite(g).all()
+    idx = sorted({0, 511, *np.random.default_rng(11).choice(np.arange(1, 511), 14, replace=False).tolist()})
+    assert len(idx) == 16
+    s = inputs.subset(b, idx)
+    o = oracle.eri_md4(b.ls, s.centers, s.exps, s.coefs, s.nprim)
+    for i, q in enumerate(idx):
+        assert_close(g[q], o[i], ("iiii K5", q))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("ls,seed", [((7, 7, 7, 7), 1005), ((6, 7, 6, 7), 1007)])
+def test_l7_classes_k3_through_the_plan_kernel(torch, ls, seed):
+    b = inputs.class_batch(ls, 256, 3, seed=seed, exp_range=(0.05, 200.0))
+    lq = np.tile(np.array(ls, np.int32), (b.nq, 1))
+    p = eri4.Plan(lq, b.nprim, b.kmax)
+    g = p.execute(dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    assert np.isfinite(g).all()
+    bl = inputs.Batch(None, b.centers, b.exps, b.coefs, b.nprim, lq)
+    check_plan(g, p.offsets(), bl, [0, 255])
+
+
+def _tuned_tiles():
+    path = os.path.join(ROOT, "paper_2307_03452_amd", "tune_mi355x.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)["entries"]
+
+
+K_BUCKETS = ((1, 1), (2, 40), (41, 400), (401, 4096))
+
+
+def stratified_sample(b, nclasses=5, per_bucket=2, seed=13):
+    """The nclasses most common classes; in each, per bucket of
+    Ka Kb Kc Kd (K_BUCKETS), the quartet with the largest product and
+    per_bucket - 1 random others."""
+    rng = np.random.default_rng(seed)
+    cls, counts = np.unique(b.lq, axis=0, return_counts=True)
+    top = cls[np.argsort(-counts, kind="stable")[:nclasses]]
+    kprod = b.nprim.astype(np.int64).prod(axis=1)
+    idx = []
+    for c in top:
+        inc = np.flatnonzero((b.lq == c).all(axis=1))
+        for lo, hi in K_BUCKETS:
+            sel = inc[(kprod[inc] >= lo) & (kprod[inc] <= hi)]
+            if sel.size == 0:
+                continue
+            big = sel[np.argmax(kprod[sel])]
+            rest = sel[sel != big]
+            pick = [int(big)] + rng.choice(rest, min(per_bucket - 1, rest.size), replace=False).tolist()
+            idx.extend(pick)
+    return sorted(set(idx))
+
+
+@pytest.mark.timeout(600)
+def test_uneven_batch_stratified_through_the_plan_kernel(torch):
+    b = inputs.uneven_batch()
+    assert b.nq == 20000
+    p = eri4.Plan(b.lq, b.nprim, b.kmax, tiles=_tuned_tiles())
+    g = p.execute(dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    assert np.isfinite(g).all()
+    idx = stratified_sample(b)
+    kprod = b.nprim.astype(np.int64).prod(axis=1)
+    # every bucket of every sampled class is represented, the largest K included
+    assert len(idx) >= 30 and kprod[idx].max() > 400
+    check_plan(g, p.offsets(), b, idx)
