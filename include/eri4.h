@@ -196,6 +196,29 @@ eri4_status eri4_batch_exchange(int la, int lb, int lc, int ld, int64_t nquartet
                                 const double* dens, double* work, int64_t work_size, double* out,
                                 hipStream_t stream);
 
+/*
+ * eri4_batch_coulomb without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It calls no hipMalloc, hipFree or other
+ * allocating routine: the Hermite-space densities live in a static device
+ * array of eri4_static_scratch_bytes() bytes (32 MiB) that the library holds
+ * on each device until the process ends.  Quartets run in passes of as many
+ * as that array holds; a class whose single quartet would need more is
+ * rejected with UNSUPPORTED (no class with l <= 7 and kmax <= 16 does).
+ * eri4_init must have run on the current device (it allocates the library's
+ * tables): otherwise INVALID_ARGUMENT and nothing is enqueued.
+ * Every call on one device shares that device's array and leaves the last
+ * call's contents in it (nothing in it needs to start at zero): calls that
+ * overlap on one device (different streams or threads, with no ordering
+ * between them) race and give undefined results; calls on one stream, or
+ * otherwise ordered, do not.  Arguments, results and errors as
+ * eri4_batch_coulomb.
+ */
+int64_t eri4_static_scratch_bytes(void);
+eri4_status eri4_batch_coulomb_static(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                                      const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                                      const double* dens, double* out, hipStream_t stream);
+
 eri4_status eri4_solid_coefficients(int l, double* C);
 int64_t eri4_solid_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets);
 eri4_status eri4_batch_solid(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,

@@ -137,8 +137,18 @@ eri4_status fail(eri4_status s, const char* fmt, ...) {
   return s;
 }
 
+// Device scratch of the no-allocation Coulomb call (eri4_batch_coulomb_static):
+// the Hermite-space ket densities of one pass of quartets.  Each device holds
+// its own copy until the process ends.  Host code must never pass this name to
+// a kernel or a copy (on the host it is only a stand-in, not a device address):
+// it uses the address that hipGetSymbolAddress returned for the current device
+// (DeviceState::scratch), taken once per device in ensure_device.
+constexpr int64_t kStaticScratchDoubles = (int64_t)4 << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
 struct DeviceState {
   bool ready = false;
+  double* scratch = nullptr;  // this device's address of `scratch`
   double* boys = nullptr;
   uint2* rtab = nullptr;
   double* stab = nullptr;  // solid-harmonic coefficients (make_solid_table)
@@ -197,6 +207,7 @@ eri4_status ensure_device(DeviceState** st) {
       return fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation of the solid-harmonic table failed");
     HIP_TRY(hipMemcpy(d.stab, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
     for (int i = 0; i < 2 * (kMaxL + 1); ++i) d.rstart[i] = rs[i];
+    HIP_TRY(hipGetSymbolAddress((void**)&d.scratch, HIP_SYMBOL(scratch)));
     eri4_status s = set_attrs();
     if (s != ERI4_SUCCESS) return s;
     d.ready = true;
@@ -541,6 +552,39 @@ eri4_status eri4_batch_exchange(int la, int lb, int lc, int ld, int64_t nquartet
     if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
   }
   return ERI4_SUCCESS;
+}
+
+int64_t eri4_static_scratch_bytes(void) { return kStaticScratchDoubles * (int64_t)sizeof(double); }
+
+eri4_status eri4_batch_coulomb_static(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
+                                      const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
+                                      const double* dens, double* out, hipStream_t stream) {
+  g_err.clear();
+  eri4_status st = check_class(la, lb, lc, ld, nquartets, kmax);
+  if (st != ERI4_SUCCESS) return st;
+  if (nquartets == 0) return ERI4_SUCCESS;
+  if (!centers || !exponents || !coeffs || !nprim || !dens || !out)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
+  ClassParams p;
+  int64_t ds;
+  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds))
+    return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
+  if ((int64_t)kmax * kmax * ds > kStaticScratchDoubles)
+    return fail(ERI4_ERROR_UNSUPPORTED, "one quartet's Hermite-space densities (%lld doubles) exceed the %lld-double "
+                "static scratch", (long long)kmax * kmax * ds, (long long)kStaticScratchDoubles);
+  // no initialisation here: that allocates the tables (eri4_init must have run)
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const DeviceState* d = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev < (int)g_dev.size() && g_dev[dev].ready) d = &g_dev[dev];
+  }
+  if (!d)
+    return fail(ERI4_ERROR_INVALID_ARGUMENT, "the library is not initialised on device %d: call eri4_init there "
+                "first (it allocates; this call does not)", dev);
+  return coulomb_passes(la, lb, lc, ld, nquartets, centers, exponents, coeffs, nprim, kmax, dens, d->scratch,
+                        kStaticScratchDoubles, out, stream, d);
 }
 
 // ---------------------------------------------------------------------------

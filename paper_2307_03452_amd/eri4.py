@@ -55,7 +55,8 @@ EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version",
            "eri4_plan_create_coulomb", "eri4_plan_execute_coulomb",
            "eri4_boys", "eri4_hermite_r", "eri4_hermite_e", "eri4_solid_coefficients", "eri4_solid_work_size",
            "eri4_batch_solid", "eri4_coulomb_work_size", "eri4_batch_coulomb", "eri4_exchange_work_size",
-           "eri4_batch_exchange")
+           "eri4_batch_exchange", "eri4_static_scratch_bytes",
+           "eri4_batch_coulomb_static")
 
 _lib = None
 
@@ -98,6 +99,10 @@ def lib() -> ctypes.CDLL:
         L.eri4_exchange_work_size.restype = i64
         L.eri4_batch_exchange.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp, i64, vp, vp]
         L.eri4_batch_exchange.restype = c_int
+        L.eri4_static_scratch_bytes.argtypes = []
+        L.eri4_static_scratch_bytes.restype = i64
+        L.eri4_batch_coulomb_static.argtypes = [c_int] * 4 + [i64, vp, vp, vp, vp, c_int, vp, vp, vp]
+        L.eri4_batch_coulomb_static.restype = c_int
         L.eri4_plan_create.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int]
         L.eri4_plan_create.restype = c_int
         L.eri4_plan_create_tuned.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int, vp, c_int]
@@ -302,6 +307,25 @@ def batch_exchange(ls, centers, exps, coefs, nprim, dens, work=None, out=None, s
     _check(lib().eri4_batch_exchange(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
                                      _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax, _ptr(dens, "float64"),
                                      _ptr(work, "float64"), work.numel(), _ptr(out, "float64"), _stream(stream)))
+    return out
+
+
+def static_scratch_bytes() -> int:
+    """Bytes of the static device array eri4_batch_coulomb_static works in."""
+    return int(lib().eri4_static_scratch_bytes())
+
+
+def batch_coulomb_static(ls, centers, exps, coefs, nprim, dens, out, stream=None):
+    """eri4_batch_coulomb_static: batch_coulomb with no workspace and no
+    device allocation in the library call (the caller passes out, float64
+    [nq, Na, Nb]; init() must have run on the device)."""
+    la, lb, lc, ld = (int(x) for x in ls)
+    nq, kmax = _check_shells(centers, exps, coefs, nprim)
+    _check_out(out, nq * ncart(la) * ncart(lb))
+    _check_out(dens, nq * ncart(lc) * ncart(ld), "density")
+    _check(lib().eri4_batch_coulomb_static(la, lb, lc, ld, nq, _ptr(centers, "float64"), _ptr(exps, "float64"),
+                                           _ptr(coefs, "float64"), _ptr(nprim, "int32"), kmax,
+                                           _ptr(dens, "float64"), _ptr(out, "float64"), _stream(stream)))
     return out
 
 
