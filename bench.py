@@ -98,22 +98,24 @@ def md4_flops_batch(lq, nprim):
     return tot
 
 
-TUNE_FILE = os.path.join(ROOT, "paper_2307_03452_amd", "tune_mi355x.json")
+TUNE_FILE = os.path.join(ROOT, "paper_2307_03452_amd", "tune_gfx950.txt")
 
 
 def tuned_tiles():
-    """The autotuner's table (paper_2307_03452_amd/autotune.py), if present."""
+    """The autotuner's tile table (paper_2307_03452_amd/autotune.py) as tile
+    choices, for the pair-list plans; quartet plans read the file through the
+    library (tune_file)."""
     if not os.path.exists(TUNE_FILE):
         return None
-    with open(TUNE_FILE) as f:
-        return json.load(f)["entries"]
+    from paper_2307_03452_amd import eri4
+    return eri4.read_tile_table(TUNE_FILE)
 
 
-def time_plan(b, precision, steps, warmup, tiles=None):
+def time_plan(b, precision, steps, warmup, tiles=None, tune_file=None):
     """One plan over batch b (inputs resident in HBM): wall seconds per execute."""
     import torch
     from paper_2307_03452_amd import eri4
-    plan = eri4.Plan(b.lq, b.nprim, b.kmax, precision=precision, tiles=tiles)
+    plan = eri4.Plan(b.lq, b.nprim, b.kmax, precision=precision, tiles=tiles, tune_file=tune_file)
     d = lambda a: torch.from_numpy(a).cuda()
     C, E, Co = d(b.centers), d(b.exps), d(b.coefs)
     out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
@@ -166,17 +168,17 @@ def time_uneven(steps, warmup, nq=20000, seed=1004, mixed_steps=0):
     mixed_steps > 0 the same batch also runs with FP32 transforms."""
     from paper_2307_03452_amd import inputs
     b = inputs.uneven_batch(nq=nq, seed=seed)
-    tiles = tuned_tiles()
-    plan, out, wall = time_plan(b, "fp64", steps, warmup, tiles)
+    tf = TUNE_FILE if os.path.exists(TUNE_FILE) else None
+    plan, out, wall = time_plan(b, "fp64", steps, warmup, tune_file=tf)
     flops = md4_flops_batch(b.lq, b.nprim)
     rec = {"workload": UNEVEN_DESC.format(nq=nq),
            "value": plan.output_size / wall, "unit": "integrals/s", "ms_per_step": wall * 1e3,
            "md4_tflops": flops / wall / 1e12, "pct_fp64_peak": 100 * flops / wall / 1e12 / FP64_PEAK_TFLOPS,
            "parity_max_rel_err_sampled": sampled_oracle_err(b, plan, out), "quartets": nq,
-           "tiles": "autotuned table (tune_mi355x.json)" if tiles else "library default"}
+           "tiles": "autotuned table (tune_gfx950.txt, read by eri4_plan_create_tunefile)" if tf else "library default"}
     mixed = None
     if mixed_steps > 0:
-        plan32, out32, wall32 = time_plan(b, "fp32", mixed_steps, 1, tiles)
+        plan32, out32, wall32 = time_plan(b, "fp32", mixed_steps, 1, tune_file=tf)
         mixed = {"workload": UNEVEN_DESC.format(nq=nq), "precision": "fp32",
                  "transforms": "operands rounded to FP32, FP32 matrix cores, FP32 accumulation; "
                                "Boys, R and E in FP64",
@@ -206,7 +208,7 @@ def time_classes_l7(reps=1):
         torch.cuda.synchronize()
         t64 = (time.perf_counter() - t0) / reps
         b.lq = np.tile(np.array(ls, np.int32), (b.nq, 1))
-        _, o32, t32 = time_plan(b, "fp32", reps, 1)
+        _, o32, t32 = time_plan(b, "fp32", reps, 1, tune_file=TUNE_FILE if os.path.exists(TUNE_FILE) else None)
         err = float((o32 - o.reshape(-1)).abs().max())
         flops = b.nq * metrics.md4_flops(*ls, 9, 9)
         ints = b.nq * metrics.integrals_per_quartet(*ls)
@@ -441,6 +443,59 @@ def time_coulomb(reps=3):
     return out
 
 
+def time_exchange(reps=3):
+    """Exchange contraction without forming (ab|cd) (eri4_batch_exchange):
+    (ii|ii) K=1 on the 512-quartet batch and K=5 per shell on its first 128
+    quartets, next to forming the same integrals.  FLOPs: the first transform
+    2 Nab' (Kb Np)(Kk Nq) over the padded bra rows Nab' = Nb 16 ceil(Na/16), and
+    the contraction with F^b 2 Nab' Kk Nq Nc; F^b itself costs
+    2 Kk Nb Nq Nc Nd on the vector units."""
+    import torch
+    from paper_2307_03452_amd import eri4, inputs, metrics
+    import oracle
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = []
+    for K, nq in ((1, 512), (5, 128)):
+        b = inputs.subset(inputs.iiii(K=K), range(nq))
+        D = inputs.exchange_densities(b, seed=1500 + K)
+        C, E, Co, N, Dd = d(b.centers), d(b.exps), d(b.coefs), d(b.nprim), d(D)
+        work = torch.empty(eri4.exchange_work_size(b.ls, b.kmax, nq), dtype=torch.float64, device="cuda")
+        o = eri4.batch_exchange(b.ls, C, E, Co, N, Dd, work=work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eri4.batch_exchange(b.ls, C, E, Co, N, Dd, work=work, out=o)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        ints = eri4.batch(b.ls, C, E, Co, N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eri4.batch(b.ls, C, E, Co, N, out=ints)
+        torch.cuda.synchronize()
+        t_ints = (time.perf_counter() - t0) / reps
+        del ints
+        kb = K * K
+        npp = metrics.nherm(12)
+        rows = 28 * 32
+        flops = nq * (2 * rows * (kb * npp) * (kb * npp) + 2 * rows * kb * npp * 28)
+        I = oracle.eri_md4(b.ls, b.centers[:2], b.exps[:2], b.coefs[:2], b.nprim[:2])
+        ref = np.einsum("qabcd,qbd->qac", I, D[:2])
+        bound = np.einsum("qabcd,qbd->qac", np.abs(I), np.abs(D[:2]))
+        g = o[:2].cpu().numpy()
+        err = max(float(np.abs(g[i] - ref[i]).max() / bound[i].max()) for i in range(2))
+        out.append({"workload": "(ii|ii) exchange contraction K_ac = sum_bd (ab|cd) D_bd, K=%d per shell, %d quartets"
+                                % (K, nq), "ms_per_step": t * 1e3, "integrals_ms_per_step_same_batch": t_ints * 1e3,
+                    "speedup_vs_forming_integrals": t_ints / t,
+                    "pct_fp64_peak": 100 * flops / t / 1e12 / FP64_PEAK_TFLOPS,
+                    "output_bytes": nq * 28 * 28 * 8, "integral_bytes_not_written": nq * 784 * 784 * 8,
+                    "workspace_bytes": work.numel() * 8,
+                    "integrals_contracted_per_s": nq * 784 * 784 / t,
+                    "parity_max_err_2q_rel_contraction_bound": err})
+        del work, o
+    return out
+
+
 def time_stream(nq=50000, seed=1006, chunk=1024, ring=4):
     """Serving-style stream: 50 000 quartets over the 256 classes in {4..7}^4
     (Zipf counts, K=3 per shell) in chunks of 1024, each chunk a HIP graph
@@ -459,7 +514,9 @@ def time_stream(nq=50000, seed=1006, chunk=1024, ring=4):
                        f"into a ring of {ring} output buffers", "chunks": len(starts)}
     check = {}
     for prec in ("fp64", "fp32"):
-        plans = [eri4.Plan(b.lq[s0:s0 + chunk], b.nprim[s0:s0 + chunk], b.kmax, precision=prec) for s0 in starts]
+        tf = TUNE_FILE if os.path.exists(TUNE_FILE) else None
+        plans = [eri4.Plan(b.lq[s0:s0 + chunk], b.nprim[s0:s0 + chunk], b.kmax, precision=prec, tune_file=tf)
+                 for s0 in starts]
         size = max(p.output_size for p in plans)
         outs = [torch.empty(size, dtype=torch.float64, device="cuda") for _ in range(ring)]
         side = torch.cuda.Stream()
@@ -672,6 +729,7 @@ def main():
     if args.solid_steps > 0 and args.workload == "iiii_k1":
         rec["solid"] = time_solid(args.solid_steps)
         rec["coulomb"] = time_coulomb(args.solid_steps)
+        rec["exchange"] = time_exchange(args.solid_steps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

@@ -294,6 +294,23 @@ typedef struct {
 eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
                                    int kmax, eri4_precision precision, const eri4_tile_choice* choices,
                                    int nchoices);
+
+/*
+ * eri4_plan_create_tuned with the choices read from a tile table file (what
+ * the autotuner writes), so that a plan can be built from the table alone.
+ * tune_file: path of a text file, or NULL for the library's own choices.
+ * Format: '#' starts a comment line; one line "arch <name>" (e.g. "arch
+ * gfx950") before the entries; then one entry per line,
+ *   la lb lc ld kq_min kq_max rows16 layout
+ * with layout one of box, slab, box2 (fields as eri4_tile_choice).  The
+ * table applies only to the architecture it names: a file whose arch differs
+ * from the current device's (hipDeviceProp_t::gcnArchName up to its first
+ * ':') gives INVALID_ARGUMENT, as do an unreadable file, a malformed line and
+ * a missing arch line (the message names the file and line).  Otherwise as
+ * eri4_plan_create_tuned.
+ */
+eri4_status eri4_plan_create_tunefile(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
+                                      int kmax, eri4_precision precision, const char* tune_file);
 int64_t eri4_plan_output_size(eri4_plan plan);                         /* doubles; -1 if plan is NULL */
 eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets); /* HOST int64 [nquartets]; Coulomb plans: [nbra] */
 eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents,

@@ -12,7 +12,7 @@ INC = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liberi4.so")
 STAGES_LIB = os.path.join(HERE, "liberi4_stages.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["eri4_plan64.hip", "eri4_plan32.hip", "eri4_plan64p.hip", "eri4_plan32p.hip", "eri4_fused.hip",
+SOURCES = ["eri4_plan64.hip", "eri4_plan32.hip", "eri4_plan64p.hip", "eri4_plan32p.hip", "eri4_fused.hip", "eri4_small.hip",
            "eri4_solid.hip", "eri4_coulomb.hip", "eri4_exchange.hip", "eri4.hip", "eri4_tables.cpp"]
 HEADERS = ["eri4_device.h", "eri4_internal.h", "eri4_launch.h"]
 

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -166,6 +167,7 @@ std::deque<DeviceState> g_dev;  // a deque: growing it keeps pointers to existin
 
 eri4_status set_attrs() {
   HIP_TRY(fused_set_attrs());
+  HIP_TRY(small_set_attrs());
   HIP_TRY(solid_set_attrs());
   HIP_TRY(plan_solid_set_attrs());
   HIP_TRY(coulomb_set_attrs());
@@ -286,6 +288,24 @@ bool pick_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d,
   return false;
 }
 
+// The one-wave kernel's parameters for classes whose shells all have l <=
+// kSmallLMax: box layout, rb = bra row blocks per pass (at most 3, with at
+// most 12 first-transform accumulator blocks of 16 x 16).
+bool small_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* out) {
+  if (la > kSmallLMax || lb > kSmallLMax || lc > kSmallLMax || ld > kSmallLMax) return false;
+  const int nrb = (ncart(la) * ncart(lb) + 15) / 16, nqb = (nherm(lc + ld) + 15) / 16;
+#ifndef ERI4_SMALL_RGMAX
+#define ERI4_SMALL_RGMAX 3
+#endif
+  int rg = std::min(nrb, ERI4_SMALL_RGMAX);
+  while (rg > 1 && rg * nqb > 12) --rg;
+  ClassParams p = make_params(la, lb, lc, ld, kmax, rg, false, false);
+  if (p.lds_bytes > kSmallLdsMax || p.nqb > 6) return false;
+  p.rtab_off = d ? d->rstart[p.L] : 0;
+  *out = p;
+  return true;
+}
+
 // Solid-harmonic output: the library's tile for the class, with rows and
 // columns over the 2l+1 real solid harmonics of each shell; hbs / hks doubles
 // of H per bra / ket primitive pair (rows padded to whole tiles, columns to
@@ -350,6 +370,16 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets, const 
   eri4_status s = ensure_device(&d);
   if (s != ERI4_SUCCESS) return s;
   ClassParams p;
+  if (small_params(la, lb, lc, ld, kmax, d, &p)) {
+    const int64_t qchunk = (int64_t)1 << 30;
+    for (int64_t q0 = 0; q0 < nquartets; q0 += qchunk) {
+      const int64_t nq = std::min(qchunk, nquartets - q0);
+      const hipError_t e =
+          small_launch(p, nq, stream, Tables{d->boys, d->rtab}, centers, exponents, coeffs, nprim, out, q0);
+      if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
+    }
+    return ERI4_SUCCESS;
+  }
   if (!pick_params(la, lb, lc, ld, kmax, d, kMaxLdsBytes, &p))
     return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
   const int64_t max_blocks = (int64_t)1 << 30;
@@ -826,6 +856,77 @@ eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int
                                    int nchoices) {
   g_err.clear();
   return plan_create(plan, nquartets, l, nprim, kmax, precision, choices, nchoices, false, 0, 0, false);
+}
+
+// Tile table file (format in eri4.h) -> choices; checks the arch line against
+// the current device.
+static eri4_status read_tile_table(const char* path, std::vector<eri4_tile_choice>* out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(ERI4_ERROR_INVALID_ARGUMENT, "tile table %s: cannot open it", path);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    std::fclose(f);
+    return fail(ERI4_ERROR_HIP, "tile table %s: no device properties", path);
+  }
+  std::string devarch(prop.gcnArchName);
+  devarch = devarch.substr(0, devarch.find(':'));
+  char line[512];
+  int lineno = 0;
+  bool have_arch = false;
+  eri4_status st = ERI4_SUCCESS;
+  while (st == ERI4_SUCCESS && std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    char* p = line;
+    while (*p == ' ' || *p == '\t') ++p;
+    if (*p == '#' || *p == '\n' || *p == '\r' || *p == 0) continue;
+    char word[64];
+    if (std::sscanf(p, "arch %63s", word) == 1 && std::strncmp(p, "arch", 4) == 0) {
+      if (devarch != word)
+        st = fail(ERI4_ERROR_INVALID_ARGUMENT, "tile table %s is for %s, the device is %s", path, word,
+                  devarch.c_str());
+      have_arch = true;
+      continue;
+    }
+    eri4_tile_choice c{};
+    char lay[16];
+    int n = 0;
+    if (std::sscanf(p, "%d %d %d %d %d %d %d %15s %n", &c.l[0], &c.l[1], &c.l[2], &c.l[3], &c.kq_min, &c.kq_max,
+                    &c.rows16, lay, &n) != 8 || p[n] != 0) {
+      st = fail(ERI4_ERROR_INVALID_ARGUMENT, "tile table %s line %d: expected 'la lb lc ld kq_min kq_max rows16 "
+                "layout'", path, lineno);
+      break;
+    }
+    if (!have_arch) {
+      st = fail(ERI4_ERROR_INVALID_ARGUMENT, "tile table %s line %d: entry before the arch line", path, lineno);
+      break;
+    }
+    if (!std::strcmp(lay, "box")) c.layout = ERI4_LAYOUT_BOX;
+    else if (!std::strcmp(lay, "slab")) c.layout = ERI4_LAYOUT_SLAB;
+    else if (!std::strcmp(lay, "box2")) c.layout = ERI4_LAYOUT_BOX2;
+    else {
+      st = fail(ERI4_ERROR_INVALID_ARGUMENT, "tile table %s line %d: unknown layout %s", path, lineno, lay);
+      break;
+    }
+    out->push_back(c);
+  }
+  std::fclose(f);
+  if (st == ERI4_SUCCESS && !have_arch) st = fail(ERI4_ERROR_INVALID_ARGUMENT, "tile table %s: no arch line", path);
+  return st;
+}
+
+eri4_status eri4_plan_create_tunefile(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
+                                      int kmax, eri4_precision precision, const char* tune_file) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
+  *plan = nullptr;
+  std::vector<eri4_tile_choice> choices;
+  if (tune_file) {
+    const eri4_status st = read_tile_table(tune_file, &choices);
+    if (st != ERI4_SUCCESS) return st;
+  }
+  return plan_create(plan, nquartets, l, nprim, kmax, precision, choices.data(), (int)choices.size(), false, 0, 0,
+                     false);
 }
 
 int64_t eri4_plan_output_size(eri4_plan plan) { return plan ? plan->out_size : -1; }

@@ -178,9 +178,10 @@ __device__ void build_etab(double* E, int la, int lb, int trow, int taxis, doubl
 // offset (box: t*S2 + u*S1 + v; slab: u*S1 + v, the slab of the summed t,
 // taken from bits 24.., is added per gather).  Entries n..n_alloc-1 are
 // padding: E index (Lh+1, 0, 0), whose value is 0, and R index (0,0,0).
+template <int NT = kThreads>
 __device__ void build_htab(int2* tab, int Lh, int n, int n_alloc, int S1, int S2, bool slab, int tid) {
   const int ncol = (Lh + 1) * (Lh + 2) / 2;
-  for (int c = tid; c < ncol; c += kThreads) {
+  for (int c = tid; c < ncol; c += NT) {
     int t = 0, rem = c;
     while (rem >= Lh - t + 1) {
       rem -= Lh - t + 1;
@@ -192,7 +193,7 @@ __device__ void build_htab(int2* tab, int Lh, int n, int n_alloc, int S1, int S2
     for (int v = 0; v <= Lh - t - u; ++v)
       tab[first + v] = make_int2(t | (u << 8) | (v << 16) | (t << 24), (slab ? 0 : t * S2) + u * S1 + v);
   }
-  for (int i = n + tid; i < n_alloc; i += kThreads) tab[i] = make_int2(Lh + 1, 0);
+  for (int i = n + tid; i < n_alloc; i += NT) tab[i] = make_int2(Lh + 1, 0);
 }
 
 // Cartesian component index -> (x, y, z) for shell l (order ax = l..0, ay = l-ax..0).
@@ -372,11 +373,11 @@ __device__ __forceinline__ void gemm1_pair(typename Acc<F32>::type (&acc)[NR][NC
   gemm1_range<NR, NC, SLAB, F32>(acc, brae, R, ptab, rowx, rowy, rowz, offq, tq, 0, np4, L, S1, lane);
 }
 
-// Second transform for one group of NC output column blocks (cb0, cb0+8, ...)
+// Second transform for one group of NC output column blocks (cb0, cb0+CSTRIDE, ...)
 // and NR row blocks, then the output write:
 //   out[ab][cd] (+)= sum_q X[ab][q] E_cd[cd][q]
 // E_cd is the product of three ket-table entries (sign of eq. (pq) folded in).
-template <int NR, int NC, bool F32>
+template <int NR, int NC, bool F32, int CSTRIDE = 8>
 __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double* __restrict__ X,
                                             const double* __restrict__ kete, const int2* __restrict__ qtab,
                                             int cb0, int row0, double* __restrict__ outq, bool first,
@@ -385,7 +386,7 @@ __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double*
   int kx[NC], ky[NC], kz[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int cd = (cb0 + 8 * c) * 16 + n;
+    const int cd = (cb0 + CSTRIDE * c) * 16 + n;
     if (cd < cp.ncd) {
       const int ic = cd / cp.nd, id = cd - (cd / cp.nd) * cp.nd;
       int cx, cy, cz, dx, dy, dz;
@@ -461,7 +462,7 @@ __device__ __forceinline__ void gemm2_group(const ClassParams& cp, const double*
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int cd = (cb0 + 8 * c) * 16 + n;
+      const int cd = (cb0 + CSTRIDE * c) * 16 + n;
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
         const int ab = row0 + r * 16 + acc_row<F32>(jj, g);

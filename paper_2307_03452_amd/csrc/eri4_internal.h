@@ -86,6 +86,11 @@ constexpr int kCoulLds = 64 + 8 * 64;
 // LDS of one compute unit (gfx950).
 constexpr int kMaxLdsBytes = 160 * 1024;
 
+// One-wave kernel for classes whose shells all have l <= kSmallLMax
+// (eri4_small.hip): its largest dynamic LDS.
+constexpr int kSmallLMax = 3;
+constexpr int kSmallLdsMax = 64 * 1024;
+
 // One workgroup computes a tile of 16 or 32 bra rows (ab) of one quartet.
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * 64;

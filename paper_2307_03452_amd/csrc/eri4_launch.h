@@ -1,6 +1,7 @@
 // eri4_launch.h -- host-side entry points to the kernels of liberi4 that are
-// compiled in their own translation units (eri4_fused.hip, eri4_solid.hip,
-// eri4_coulomb.hip, eri4_exchange.hip and the four eri4_plan*.hip).  Not part
+// compiled in their own translation units (eri4_fused.hip, eri4_small.hip,
+// eri4_solid.hip, eri4_coulomb.hip, eri4_exchange.hip and the four
+// eri4_plan*.hip).  Not part
 // of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -19,6 +20,12 @@ struct Tables {
 // The single-class fused kernels (one launch per class and quartet chunk).
 hipError_t fused_set_attrs();
 hipError_t fused_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
+                        const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0);
+
+// One wave per quartet (eri4_small.hip) for classes whose shells all have
+// l <= kSmallLMax: p from small_params (rb = bra row blocks per pass).
+hipError_t small_set_attrs();
+hipError_t small_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
                         const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0);
 
 // Solid-harmonic output (eri4_solid.hip): the H matrices of quartets q0..q0+nq-1

@@ -25,6 +25,8 @@ PRECISION = {"fp64": 0, "fp32": 1}
 FUNCTIONS = {"cartesian": 0, "solid": 1}
 # eri4_layout: where the Hermite integrals of a tile live in LDS
 LAYOUT = {"box": 0, "slab": 1, "box2": 2}
+# the tile table tuned on MI355X (gfx950) by autotune.py, read by the library
+TUNE_FILE = os.path.join(HERE, "tune_gfx950.txt")
 
 
 class TileChoice(ctypes.Structure):
@@ -32,6 +34,20 @@ class TileChoice(ctypes.Structure):
     whose product of the four contraction lengths is in [kq_min, kq_max]."""
     _fields_ = [("l", ctypes.c_int32 * 4), ("kq_min", ctypes.c_int32), ("kq_max", ctypes.c_int32),
                 ("rows16", ctypes.c_int32), ("layout", ctypes.c_int32)]
+
+
+def read_tile_table(path):
+    """The entries of a tile table file (format: eri4_plan_create_tunefile in
+    include/eri4.h) as tile-choice dicts, for calls that take them as a list."""
+    out = []
+    with open(path) as f:
+        for line in f:
+            w = line.split()
+            if not w or w[0].startswith("#") or w[0] == "arch":
+                continue
+            out.append({"l": [int(x) for x in w[:4]], "kq": [int(w[4]), int(w[5])], "rows16": int(w[6]),
+                        "layout": w[7]})
+    return out
 
 
 def tile_choices(entries):
@@ -52,7 +68,7 @@ STATUS = {0: "ERI4_SUCCESS", 1: "ERI4_ERROR_INVALID_ARGUMENT", 2: "ERI4_ERROR_UN
 EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version", "eri4_init",
            "eri4_batch", "eri4_plan_create", "eri4_plan_create_tuned", "eri4_plan_output_size", "eri4_plan_output_offsets",
            "eri4_plan_execute", "eri4_plan_destroy", "eri4_plan_create_pairs", "eri4_plan_execute_pairs", "eri4_plan_work_size",
-           "eri4_plan_create_coulomb", "eri4_plan_execute_coulomb",
+           "eri4_plan_create_coulomb", "eri4_plan_execute_coulomb", "eri4_plan_create_tunefile",
            "eri4_boys", "eri4_hermite_r", "eri4_hermite_e", "eri4_solid_coefficients", "eri4_solid_work_size",
            "eri4_batch_solid", "eri4_coulomb_work_size", "eri4_batch_coulomb", "eri4_exchange_work_size",
            "eri4_batch_exchange", "eri4_static_scratch_bytes",
@@ -107,6 +123,8 @@ def lib() -> ctypes.CDLL:
         L.eri4_plan_create.restype = c_int
         L.eri4_plan_create_tuned.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int, vp, c_int]
         L.eri4_plan_create_tuned.restype = c_int
+        L.eri4_plan_create_tunefile.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, c_int, ctypes.c_char_p]
+        L.eri4_plan_create_tunefile.restype = c_int
         L.eri4_plan_output_size.argtypes = [vp]
         L.eri4_plan_output_size.restype = i64
         L.eri4_plan_output_offsets.argtypes = [vp, vp]
@@ -363,10 +381,12 @@ class Plan:
 
     lq, nprim: host int32 arrays [nq, 4] (angular momenta, contraction lengths).
     precision: "fp64" or "fp32", the arithmetic of the two transforms.
-    tiles: optional tile choices (see tile_choices), e.g. an autotuner's table.
+    tiles: optional tile choices (see tile_choices), e.g. an autotuner's table;
+    tune_file: or the path of a tile table file the library reads itself
+    (eri4_plan_create_tunefile; TUNE_FILE is the one tuned here).
     """
 
-    def __init__(self, lq, nprim, kmax: int, precision: str = "fp64", tiles=None):
+    def __init__(self, lq, nprim, kmax: int, precision: str = "fp64", tiles=None, tune_file=None):
         import numpy as np
         self._lq = np.ascontiguousarray(lq, dtype=np.int32)
         self._np = np.ascontiguousarray(nprim, dtype=np.int32)
@@ -375,6 +395,15 @@ class Plan:
         self.kmax = int(kmax)
         self.precision = precision
         h = ctypes.c_void_p()
+        if tune_file is not None:
+            if tiles:
+                raise ValueError("give tiles or tune_file, not both")
+            _check(lib().eri4_plan_create_tunefile(
+                ctypes.byref(h), self.nq, self._lq.ctypes.data_as(ctypes.c_void_p),
+                self._np.ctypes.data_as(ctypes.c_void_p), self.kmax,
+                PRECISION[precision] if isinstance(precision, str) else int(precision), str(tune_file).encode()))
+            self._h = h
+            return
         arr = tile_choices(tiles) if tiles else None
         _check(lib().eri4_plan_create_tuned(
             ctypes.byref(h), self.nq, self._lq.ctypes.data_as(ctypes.c_void_p),

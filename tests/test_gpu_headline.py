@@ -8,7 +8,8 @@ sizes and in the launch configurations that bench.py times.
 - (kk|kk) and (ik|ik), K = 3 per shell, 256 quartets each: the FP64 plan
   kernel over each batch, 2 quartets of each against the oracle.
 - The uneven 20 000-quartet batch (classes in {4,5,6}^4, K in 1..8 per shell,
-  seed 1004) through the FP64 plan kernel with the autotuned tiles: a
+  seed 1004) through the FP64 plan kernel with the autotuned tile table read
+  by the library (eri4_plan_create_tunefile), as bench.py runs it: a
   stratified sample of the five most common classes, two quartets per bucket
   of K_a K_b K_c K_d, including each bucket's largest.
 
@@ -16,7 +17,6 @@ Tolerance: per quartet, max |gpu - oracle| <= 1e-12 max |oracle| (Sec. 2's
 transforms in FP64; the reading of the tolerance is the same as for every
 other FP64 parity test).
 """
-import json
 import os
 
 import numpy as np
@@ -116,14 +116,6 @@ def test_l7_classes_k3_through_the_plan_kernel(torch, ls, seed):
     check_plan(g, p.offsets(), bl, [0, 255])
 
 
-def _tuned_tiles():
-    path = os.path.join(ROOT, "paper_2307_03452_amd", "tune_mi355x.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        return json.load(f)["entries"]
-
-
 K_BUCKETS = ((1, 1), (2, 40), (41, 400), (401, 4096))
 
 
@@ -153,7 +145,7 @@ def stratified_sample(b, nclasses=5, per_bucket=2, seed=13):
 def test_uneven_batch_stratified_through_the_plan_kernel(torch):
     b = inputs.uneven_batch()
     assert b.nq == 20000
-    p = eri4.Plan(b.lq, b.nprim, b.kmax, tiles=_tuned_tiles())
+    p = eri4.Plan(b.lq, b.nprim, b.kmax, tune_file=eri4.TUNE_FILE)
     g = p.execute(dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs))
     torch.cuda.synchronize()
     g = g.cpu().numpy()

@@ -320,3 +320,32 @@ def test_low_l_classes_at_the_papers_contraction_sizes(torch, l, K):
     g = run_gpu(torch, b)
     o = oracle.eri_md4(b.ls, b.centers, b.exps, b.coefs, b.nprim)
     assert_quartets_close(g, o, label=(l, K))
+
+
+def test_every_class_up_to_f_through_the_one_wave_kernel(torch):
+    """Classes whose four shells all have l <= 3 run one quartet per wave
+    (eri4_small.hip): all 256 of them, mixed contraction lengths, against the
+    oracle; and against the 8-wave tile kernel (which plans use) on a mixed
+    batch of them."""
+    rng = np.random.default_rng(12)
+    for la in range(4):
+        for lb in range(4):
+            for lc in range(4):
+                for ld in range(4):
+                    ls = (la, lb, lc, ld)
+                    b = inputs.class_batch(ls, 2, (1, 3), seed=int(rng.integers(1 << 30)), exp_range=(0.05, 50.0),
+                                           kmax=3)
+                    g = run_gpu(torch, b)
+                    o = oracle.eri_md4(ls, b.centers, b.exps, b.coefs, b.nprim)
+                    assert_quartets_close(g, o, label=ls)
+    m = inputs.uneven_batch(nq=120, seed=31, lvals=(0, 1, 2, 3), kmax=3)
+    p = eri4.Plan(m.lq, m.nprim, m.kmax)
+    gp = p.execute(dev(torch, m.centers), dev(torch, m.exps), dev(torch, m.coefs))
+    torch.cuda.synchronize()
+    gp = gp.cpu().numpy()
+    off = p.offsets()
+    for q in range(m.nq):
+        s = inputs.subset(m, [q])
+        gq = run_gpu(torch, s, ls=tuple(int(x) for x in m.lq[q]))[0]
+        ref = gp[off[q]:off[q] + gq.size].reshape(gq.shape)
+        assert np.abs(gq - ref).max() <= 1e-13 * max(np.abs(ref).max(), ZERO_SCALE), q

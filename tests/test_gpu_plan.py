@@ -167,3 +167,29 @@ def test_empty_plan(torch):
               torch.zeros(0, 4, 1, dtype=torch.float64, device="cuda"),
               out=torch.zeros(1, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
+
+
+def test_tile_table_file_gives_the_plan_of_its_entries(torch, tmp_path):
+    """eri4_plan_create_tunefile reads the committed table and builds the plan
+    its entries give through eri4_plan_create_tuned (same bits); tables for
+    another architecture, malformed lines and missing files are refused."""
+    b = mixed(40, 26, (4, 5, 6), 3)
+    C, E, Co = dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs)
+    via_file = eri4.Plan(b.lq, b.nprim, b.kmax, tune_file=eri4.TUNE_FILE).execute(C, E, Co)
+    via_list = eri4.Plan(b.lq, b.nprim, b.kmax, tiles=eri4.read_tile_table(eri4.TUNE_FILE)).execute(C, E, Co)
+    torch.cuda.synchronize()
+    assert torch.equal(via_file, via_list)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    with open(eri4.TUNE_FILE) as f:
+        assert f"arch {arch}\n" in f.read()
+    bad = {"other_arch.txt": "arch gfx000\n4 4 4 4 1 1 2 box\n",
+           "no_arch.txt": "4 4 4 4 1 1 2 box\n",
+           "bad_line.txt": f"arch {arch}\n4 4 4 4 1 1 2\n",
+           "bad_layout.txt": f"arch {arch}\n4 4 4 4 1 1 2 cube\n"}
+    for name, text in bad.items():
+        p = tmp_path / name
+        p.write_text(text)
+        with pytest.raises(eri4.Eri4Error, match="tile table"):
+            eri4.Plan(b.lq, b.nprim, b.kmax, tune_file=str(p))
+    with pytest.raises(eri4.Eri4Error, match="cannot open"):
+        eri4.Plan(b.lq, b.nprim, b.kmax, tune_file=str(tmp_path / "missing.txt"))

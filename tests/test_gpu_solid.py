@@ -1,8 +1,12 @@
 """Solid-harmonic output (eri4_batch_solid) against the oracle: its Cartesian
 integrals transformed by its own coefficient table.
 
-Tolerance: 1e-12 times the quartet's largest sum_k |C x C x C x C|[m, k] |cart[k]|
-(cart: its Cartesian integrals).  Solid functions of distant shells have no low
+Tolerance: TOL times the quartet's largest sum_k |C x C x C x C|[m, k] |cart[k]|
+(cart: its Cartesian integrals), with TOL = 1e-13 for classes whose shells all
+have l <= 3 and 1e-14 above.  Measured worst ratios: 2.4e-14 for the l <= 3
+classes (there the scale is close to the Cartesian maximum and both FP64 codes'
+own rounding, about 1e-14 of it, shows) and 1.4e-16 for l >= 4 (the scale is
+far above the integrals' size), so the bounds leave a factor of 4 and 70.  Solid functions of distant shells have no low
 multipoles, so their integrals can be orders of magnitude (4e7 seen here)
 below the Cartesian ones they combine, and the coefficients grow with l (row
 1-norms up to 47 for l = 6); every FP64 route through Hermite or Cartesian
@@ -17,8 +21,11 @@ from oracle import solid
 from paper_2307_03452_amd import eri4, inputs
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 ZERO_SCALE = 1e-250
+
+
+def tol(ls):
+    return 1e-13 if max(ls) <= 3 else 1e-14
 
 
 @pytest.fixture(scope="module")
@@ -52,7 +59,7 @@ def check(g, ref, cart, ls):
     for q in range(ref.shape[0]):
         scale = max(bound[q].max(), ZERO_SCALE)
         assert np.isfinite(g[q]).all(), q
-        assert np.abs(g[q] - ref[q]).max() <= TOL * scale, (q, np.abs(g[q] - ref[q]).max() / scale)
+        assert np.abs(g[q] - ref[q]).max() <= tol(ls) * scale, (q, np.abs(g[q] - ref[q]).max() / scale)
 
 
 LOW = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 0, 1, 1), (2, 1, 0, 2), (1, 2, 2, 1), (2, 2, 2, 2), (3, 0, 2, 1),
