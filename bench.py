@@ -657,6 +657,9 @@ def main():
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline workload only (every other leg and the CPU baseline off), "
                          "e.g. for a profiler run whose dispatches must all belong to one workload")
+    ap.add_argument("--legs", default=None,
+                    help="comma list of the legs to run beside the headline (secondary, uneven, mixed, l7, stream, "
+                         "low_l, pairs, gggg, solid, coulomb, exchange); default: all, unless --only-headline")
     ap.add_argument("--calibrate-copy", type=int, metavar="MIB", default=0,
                     help="instead of benchmarking, run a plain device copy (dst = src + 0) of MIB MiB of "
                          "float64 three times: the known-size kernel whose FETCH_SIZE/WRITE_SIZE counters "
@@ -707,29 +710,50 @@ def main():
                      "algorithmic_unit": "MD4 matrix FLOPs per quartet x quartets per launch"},
     }
     rec["parity_max_rel_err"] = parity_sample(wl, b, out)
-    if args.secondary_steps > 0 and args.workload == "iiii_k1":
+    legs = {"secondary": args.secondary_steps > 0, "uneven": args.uneven_steps > 0, "mixed": args.mixed_steps > 0,
+            "l7": args.stream_steps > 0, "stream": args.stream_steps > 0, "low_l": args.stream_steps > 0,
+            "pairs": args.stream_steps > 0, "gggg": args.stream_steps > 0, "solid": args.solid_steps > 0,
+            "coulomb": args.solid_steps > 0, "exchange": args.solid_steps > 0}
+    if args.legs is not None:
+        chosen = {x for x in args.legs.split(",") if x}
+        unknown = chosen - set(legs)
+        if unknown:
+            sys.exit(f"unknown legs: {sorted(unknown)}")
+        legs = {k: k in chosen for k in legs}
+    if args.workload != "iiii_k1":
+        legs = {k: False for k in legs}
+    reps = max(1, args.solid_steps)
+    if legs["secondary"]:
         wl5 = WORKLOADS["iiii_k5"]
         b5 = make_batch(wl5)
-        _, wall5, lm5 = time_gpu(wl5, b5, args.secondary_steps, 1)
+        nsec = max(1, args.secondary_steps)
+        _, wall5, lm5 = time_gpu(wl5, b5, nsec, 1)
         f5 = b5.nq * metrics.md4_flops(*ls, 25, 25)
         s5 = sum(lm5) / len(lm5) / 1e3
-        rec["secondary"] = {"workload": wl5["desc"], "value": ints / (wall5 / args.secondary_steps),
-                            "unit": "integrals/s", "ms_per_step": wall5 * 1e3 / args.secondary_steps,
+        rec["secondary"] = {"workload": wl5["desc"], "value": ints / (wall5 / nsec),
+                            "unit": "integrals/s", "ms_per_step": wall5 * 1e3 / nsec,
                             "md4_tflops": f5 / s5 / 1e12, "pct_fp64_peak": 100 * f5 / s5 / 1e12 / FP64_PEAK_TFLOPS}
-    if args.uneven_steps > 0 and args.workload == "iiii_k1":
-        rec["uneven"], mixed = time_uneven(args.uneven_steps, 1, mixed_steps=args.mixed_steps)
+    if legs["uneven"] or legs["mixed"]:
+        rec["uneven"], mixed = time_uneven(max(1, args.uneven_steps), 1,
+                                           mixed_steps=max(1, args.mixed_steps) if legs["mixed"] else 0)
         if mixed is not None:
             rec["mixed_precision"] = mixed
-    if args.stream_steps > 0 and args.workload == "iiii_k1":
+    if legs["l7"]:
         rec["l7_classes"] = time_classes_l7()
+    if legs["stream"]:
         rec["stream"] = time_stream()
+    if legs["low_l"]:
         rec["low_l"] = time_low_l()
+    if legs["pairs"]:
         rec["pairs"] = time_pairs()
+    if legs["gggg"]:
         rec["gggg_k1"] = time_gggg()
-    if args.solid_steps > 0 and args.workload == "iiii_k1":
-        rec["solid"] = time_solid(args.solid_steps)
-        rec["coulomb"] = time_coulomb(args.solid_steps)
-        rec["exchange"] = time_exchange(args.solid_steps)
+    if legs["solid"]:
+        rec["solid"] = time_solid(reps)
+    if legs["coulomb"]:
+        rec["coulomb"] = time_coulomb(reps)
+    if legs["exchange"]:
+        rec["exchange"] = time_exchange(reps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, b)
         rec["cpu_baseline"] = cb

@@ -130,12 +130,13 @@ __device__ double boys_fm(int m, double T, const double* __restrict__ tab) {
 
 // One step of the E recursions that follow eq. (cart2herm-2):
 //   E^t <- (1/(2 zp)) E^(t-1) + c E^t + (t+1) E^(t+1),  c = P-A or P-B.
-__device__ __forceinline__ void etab_step(double (&e)[16], double h, double c) {
+template <int NT>
+__device__ __forceinline__ void etab_step(double (&e)[NT], double h, double c) {
   double prev = 0.0;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
+  for (int t = 0; t < NT; ++t) {
     const double cur = e[t];
-    const double nxt = (t + 1 < 16) ? e[t + 1] : 0.0;
+    const double nxt = (t + 1 < NT) ? e[t + 1] : 0.0;
     e[t] = h * prev + c * cur + (double)(t + 1) * nxt;
     prev = cur;
   }
@@ -146,6 +147,8 @@ __device__ __forceinline__ void etab_step(double (&e)[16], double h, double c) {
 // (t > a+b are 0, in particular the last one).  Each axis ends with an all-zero
 // row at row index (la+1)*(lb+1), used for padding rows.  alt_sign multiplies
 // entry t by (-1)^t (the ket side of eq. (pq)).
+// TMAX (at least la+lb+1) entries of each recursion are kept in registers.
+template <int TMAX = 16>
 __device__ void build_etab(double* E, int la, int lb, int trow, int taxis, double h,
                            const double* PA, const double* PB, bool alt_sign, int lane) {
   const int na = la + 1;
@@ -157,17 +160,17 @@ __device__ void build_etab(double* E, int la, int lb, int trow, int taxis, doubl
     const int axis = lane / na;
     const int a = lane - axis * na;
     const double pa = PA[axis], pb = PB[axis];
-    double e[16];
+    double e[TMAX];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) e[t] = (t == 0) ? 1.0 : 0.0;
+    for (int t = 0; t < TMAX; ++t) e[t] = (t == 0) ? 1.0 : 0.0;
     for (int s = 0; s < a; ++s) etab_step(e, h, pa);
     double* base = E + axis * taxis + a * (lb + 1) * trow;
     for (int b = 0; b <= lb; ++b) {
       double* row = base + b * trow;
 #pragma unroll
-      for (int t = 0; t < 16; ++t)
+      for (int t = 0; t < TMAX; ++t)
         if (t < trow) row[t] = (alt_sign && (t & 1)) ? -e[t] : e[t];
-      for (int t = 16; t < trow; ++t) row[t] = 0.0;  // beyond a+b <= 14
+      for (int t = TMAX; t < trow; ++t) row[t] = 0.0;  // beyond a+b
       if (b < lb) etab_step(e, h, pb);
     }
   }

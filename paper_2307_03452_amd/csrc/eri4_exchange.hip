@@ -12,18 +12,20 @@ namespace eri4 {
 namespace {
 
 // F^b of ket primitives (z1, w1) of shell lc and (z2, w2) of shell ld at
-// centres c[0..5] for row b of the density block D[Nb][Nd], in the operand
-// order of exch_gemm: out[(cc * nq4 / 4 + s) * 64 + l] = F^b[4 s + l / 16][16 cc + l % 16],
-// zero past the nq Hermite functions and the nc components.  Called by all
-// threads of a workgroup.
-__device__ __forceinline__ void build_fb(int lc, int ld, const double* __restrict__ c, double z1, double z2,
-                                         double w1, double w2, const double* __restrict__ Db,
-                                         double* __restrict__ out, int tid) {
+// centres c[0..5], for every row b < nb of the density block D[Nb][Nd] (device
+// memory), in the operand order of exch_gemm: F^b at out + b * fbs, with
+// out[(cc * nq4 / 4 + s) * 64 + l] = F^b[4 s + l / 16][16 cc + l % 16], zero
+// past the nq Hermite functions and the nc components.  Each thread forms the
+// nd products E_cd^q of one (q, c) once and contracts them with every row of
+// D.  Called by all threads of a workgroup.
+__device__ __forceinline__ void build_f(int lc, int ld, int nb, const double* __restrict__ c, double z1, double z2,
+                                        double w1, double w2, const double* __restrict__ D,
+                                        double* __restrict__ out, int64_t fbs, int tid) {
+  constexpr int kNd = ncart(kTableLMax);
   __shared__ double tabs[kMaxEtab];
   __shared__ double pair[16];
   __shared__ int2 qt[kMaxHerm + 16];
-  __shared__ int3 cdx[ncart(kTableLMax) * ncart(kTableLMax)];  // E-table rows of each (c, d)
-  __shared__ double dv[ncart(kTableLMax)];
+  __shared__ int3 cdx[kNd * kNd];  // E-table rows of each (c, d)
   const int lane = tid & 63;
   const int Lk = lc + ld, nq = nherm(Lk), nq4 = (nq + 3) & ~3;
   const int tkrow = odd_row(Lk + 2), tkaxis = ((lc + 1) * (ld + 1) + 1) * tkrow;
@@ -38,7 +40,6 @@ __device__ __forceinline__ void build_fb(int lc, int ld, const double* __restric
     cdx[cd] = make_int3((cx * (ld + 1) + dx) * tkrow, tkaxis + (cy * (ld + 1) + dy) * tkrow,
                         2 * tkaxis + (cz * (ld + 1) + dz) * tkrow);
   }
-  if (tid < nd) dv[tid] = Db[tid];
   __syncthreads();
   if (tid < 64) build_etab(tabs, lc, ld, tkrow, tkaxis, 0.5 / pair[0], pair + 5, pair + 8, true, lane);
   __syncthreads();
@@ -47,23 +48,37 @@ __device__ __forceinline__ void build_fb(int lc, int ld, const double* __restric
     const int blk = e >> 6, l = e & 63;
     const int cc = blk / (nq4 / 4), st = blk - cc * (nq4 / 4);
     const int kq = 4 * st + (l >> 4), ic = 16 * cc + (l & 15);
-    double v = 0.0;
-    if (kq < nq && ic < nc) {
+    const bool valid = kq < nq && ic < nc;
+    double ev[kNd];
+    if (valid) {
       const int hx = qt[kq].x;
       const int t = hx & 0xff, u = (hx >> 8) & 0xff, w = (hx >> 16) & 0xff;
       const int3* row = cdx + ic * nd;
-      for (int id = 0; id < nd; ++id) {
-        const int3 o = row[id];
-        v += dv[id] * tabs[o.x + t] * tabs[o.y + u] * tabs[o.z + w];
+#pragma unroll
+      for (int id = 0; id < kNd; ++id) {
+        if (id < nd) {
+          const int3 o = row[id];
+          ev[id] = tabs[o.x + t] * tabs[o.y + u] * tabs[o.z + w];
+        } else {
+          ev[id] = 0.0;
+        }
       }
     }
-    out[e] = v;
+    for (int b = 0; b < nb; ++b) {
+      double v = 0.0;
+      if (valid) {
+        const double* Db = D + b * nd;
+#pragma unroll
+        for (int id = 0; id < kNd; ++id)
+          if (id < nd) v += ev[id] * Db[id];
+      }
+      out[b * fbs + e] = v;
+    }
   }
 }
 
 // One workgroup per (quartet q0 + blockIdx.x, ket pair slot blockIdx.y = k *
-// kmax + l, shell-b component blockIdx.z): F^b at
-// fb + ((blockIdx.x * kmax^2 + slot) * nb + b) * fbs.
+// kmax + l): F^b of every b at fb + ((blockIdx.x * kmax^2 + slot) * nb + b) * fbs.
 __global__ __launch_bounds__(kThreads, 1) void exchange_f_kernel(
     const ClassParams cp, const double* __restrict__ centers, const double* __restrict__ exps,
     const double* __restrict__ coefs, const int32_t* __restrict__ nprim, const double* __restrict__ dens,
@@ -71,14 +86,14 @@ __global__ __launch_bounds__(kThreads, 1) void exchange_f_kernel(
   const int tid = threadIdx.x;
   const int64_t iq = blockIdx.x;
   const int64_t q = q0 + iq;
-  const int slot = blockIdx.y, ib = blockIdx.z, kmax = cp.kmax;
+  const int slot = blockIdx.y, kmax = cp.kmax;
   const int k = slot / kmax, l = slot - (slot / kmax) * kmax;
   const int Kc = nprim[q * 4 + 2], Kd = nprim[q * 4 + 3];
   if (Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax || k >= Kc || l >= Kd) return;
   const double* e = exps + (q * 4 + 2) * kmax;
   const double* w = coefs + (q * 4 + 2) * kmax;
-  build_fb(cp.lc, cp.ld, centers + q * 12 + 6, e[k], e[kmax + l], w[k], w[kmax + l],
-           dens + (q * cp.nb + ib) * cp.nd, fb + ((iq * kmax * kmax + slot) * cp.nb + ib) * fbs, tid);
+  build_f(cp.lc, cp.ld, cp.nb, centers + q * 12 + 6, e[k], e[kmax + l], w[k], w[kmax + l], dens + q * cp.nb * cp.nd,
+          fb + (iq * kmax * kmax + slot) * cp.nb * fbs, fbs, tid);
 }
 
 // One workgroup = one quartet x one tile of RB*16 bra rows in (b, a) order
@@ -147,8 +162,8 @@ hipError_t exchange_set_attrs() {
 hipError_t exchange_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
                            const double* exps, const double* coefs, const int32_t* nprim, const double* dens,
                            double* fb, int64_t fbs, double* part, double* out, int64_t q0) {
-  hipLaunchKernelGGL(exchange_f_kernel, dim3((unsigned)nq, (unsigned)(p.kmax * p.kmax), (unsigned)p.nb),
-                     dim3(kThreads), 0, s, p, centers, exps, coefs, nprim, dens, fb, q0, fbs);
+  hipLaunchKernelGGL(exchange_f_kernel, dim3((unsigned)nq, (unsigned)(p.kmax * p.kmax)), dim3(kThreads), 0, s, p,
+                     centers, exps, coefs, nprim, dens, fb, q0, fbs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)(nq * p.nrt));

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(E
           for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
           baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (bpair[1] * kpair[1]) * F;
         }
-        build_etab(brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / bpair[0], bpair + 5, bpair + 8, false, lane);
+        build_etab<2 * kSmallLMax + 2>(brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / bpair[0], bpair + 5, bpair + 8, false, lane);
         __syncthreads();
         hermite_r_wave(R, baseM, cp.L, pqv, ent, lane);
         gemm1_range<RG, NCQ, false, false>(acc1, brae, R, ptab, rowx, rowy, rowz, offq, tq, 0, cp.np4, cp.L, cp.S1,
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(E
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj)
             X[(r * 16 + acc_row<false>(jj, lane >> 4)) * cp.xs + c * 16 + (lane & 15)] = acc1[r][c][jj];
-      build_etab(kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / kpair[0], kpair + 5, kpair + 8, true, lane);
+      build_etab<2 * kSmallLMax + 2>(kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / kpair[0], kpair + 5, kpair + 8, true, lane);
       __syncthreads();
       small_gemm2<RG>(cp, X, kete, qtab, row0, outq, kl == 0, lane);
       __syncthreads();

@@ -42,7 +42,9 @@ def _grid(row):
 
 
 def _short(name):
-    """Kernel name without its parameter list."""
+    """Kernel name without its parameter list (and without the anonymous
+    namespace, whose parentheses would cut it short)."""
+    name = name.replace("(anonymous namespace)::", "")
     i = name.find(">(")
     return name[:i + 1] if i >= 0 else name.split("(")[0]
 

@@ -28,7 +28,9 @@ FP64_PEAK_TFLOPS = 78.6
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workloads", nargs="*", default=["iiii_k1", "iiii_k5", "gggg_k1"])
+    ap.add_argument("--workloads", nargs="*", default=["iiii_k1", "iiii_k5", "gggg_k1", "gggg_k3"],
+                    help="bench.py workloads, or gggg_k3: (gg|gg) with 3 primitives per shell, 2048 quartets "
+                         "(the contracted small classes that dominate the uneven batch)")
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--k5-quartets", type=int, default=64,
                     help="quartets of the K=5 batch to time (the first ones; all 512 take 2.6 s per call)")
@@ -57,8 +59,11 @@ def main(argv=None):
     eri4.init()
     lines = ["# Stage breakdown of the fused kernel (stage-timer build)", "",
              "Command: `python -m paper_2307_03452_amd.stages " + " ".join(argv or sys.argv[1:]) + "`", ""]
+    extra = {"gggg_k3": dict(ls=(4, 4, 4, 4), K=3, nq=2048, seed=1011, exps=(0.05, 200.0),
+                             desc="(gg|gg) l=4 Cartesian, K=3 per shell, 2048 quartets, exponents log-uniform "
+                                  "[0.05,200], 8-Bohr cube")}
     for name in a.workloads:
-        wl = bench.WORKLOADS[name]
+        wl = extra[name] if name in extra else bench.WORKLOADS[name]
         b = bench.make_batch(wl)
         if name == "iiii_k5":
             b = inputs.subset(b, range(a.k5_quartets))
