@@ -347,6 +347,38 @@ def time_solid(reps=3):
                     "pct_fp64_peak": 100 * flops / t / 1e12 / FP64_PEAK_TFLOPS,
                     "workspace_bytes": work.numel() * 8, "parity_max_err_2q_rel_transform_bound": err})
         del work, o
+    # a quartet plan over solid harmonics (mixed classes, one persistent
+    # launch after the H build) beside the Cartesian plan on the same quartets
+    nq = 1024
+    b = inputs.stream_batch(nq, 1006)
+    C, E, Co = d(b.centers), d(b.exps), d(b.coefs)
+    tf = TUNE_FILE if os.path.exists(TUNE_FILE) else None
+    times = {}
+    for kind in ("solid", "cartesian"):
+        p = (eri4.SolidPlan(b.lq, b.nprim, b.kmax, tune_file=tf) if kind == "solid"
+             else eri4.Plan(b.lq, b.nprim, b.kmax, tune_file=tf))
+        work = (torch.empty(max(1, p.work_size), dtype=torch.float64, device="cuda") if kind == "solid" else None)
+        o = p.execute(C, E, Co, work=work) if work is not None else p.execute(C, E, Co)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            if work is not None:
+                p.execute(C, E, Co, out=o, work=work)
+            else:
+                p.execute(C, E, Co, out=o)
+        torch.cuda.synchronize()
+        times[kind] = (time.perf_counter() - t0) / reps
+        if work is not None:
+            wbytes = work.numel() * 8
+        del o, work, p
+    flops = sum(metrics.md4_flops(*(int(x) for x in b.lq[q]), int(b.nprim[q, 0] * b.nprim[q, 1]),
+                                  int(b.nprim[q, 2] * b.nprim[q, 3]), solid=True) for q in range(nq))
+    ints = sum(int(np.prod([2 * int(x) + 1 for x in b.lq[q]])) for q in range(nq))
+    out.append({"workload": f"solid quartet plan: {nq} quartets, classes in {{4,5,6,7}}^4 (Zipf(1.2) counts), "
+                            "K=3 per shell, one persistent launch after the H build",
+                "value": ints / times["solid"], "unit": "integrals/s", "ms_per_step": times["solid"] * 1e3,
+                "pct_fp64_peak": 100 * flops / times["solid"] / 1e12 / FP64_PEAK_TFLOPS,
+                "cartesian_plan_ms_per_step": times["cartesian"] * 1e3, "workspace_bytes": wbytes})
     return out
 
 

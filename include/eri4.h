@@ -311,6 +311,29 @@ eri4_status eri4_plan_create_tuned(eri4_plan* plan, int64_t nquartets, const int
  */
 eri4_status eri4_plan_create_tunefile(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
                                       int kmax, eri4_precision precision, const char* tune_file);
+
+/*
+ * Quartet plans over real solid harmonics: the contraction of E with the
+ * Cartesian-to-solid coefficients (Sec. 2) for a batch mixing classes and
+ * contraction lengths.  eri4_plan_create_solid takes the HOST arrays of
+ * eri4_plan_create and a tile table file (or NULL) as eri4_plan_create_tunefile;
+ * the transforms are FP64.  Quartet q's block is [2la+1][2lb+1][2lc+1][2ld+1]
+ * (conventions as eri4_batch_solid) at offsets[q], quartets in input order.
+ *
+ * eri4_plan_execute_solid takes the device arrays of eri4_plan_execute and a
+ * DEVICE workspace of at least eri4_plan_work_size(plan) doubles (contents
+ * undefined afterwards): it first builds the H matrices of the bra and the ket
+ * pair of every quartet (one per primitive pair, K_a*K_b + K_c*K_d of them per
+ * quartet), then runs the persistent kernel that reads them.  Enqueue-only and
+ * capturable, as eri4_plan_execute.  A solid quartet plan must be run with
+ * this call (eri4_plan_execute and eri4_plan_execute_pairs give
+ * INVALID_ARGUMENT), and this call takes no other plan.
+ */
+eri4_status eri4_plan_create_solid(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
+                                   int kmax, const char* tune_file);
+eri4_status eri4_plan_execute_solid(eri4_plan plan, const double* centers, const double* exponents,
+                                    const double* coeffs, double* work, int64_t work_size, double* out,
+                                    hipStream_t stream);
 int64_t eri4_plan_output_size(eri4_plan plan);                         /* doubles; -1 if plan is NULL */
 eri4_status eri4_plan_output_offsets(eri4_plan plan, int64_t* offsets); /* HOST int64 [nquartets]; Coulomb plans: [nbra] */
 eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const double* exponents,

@@ -632,8 +632,9 @@ struct eri4_plan_s {
   bool f32 = false;  // ERI4_PREC_FP32
   bool pairs = false;  // made from a bra and a ket list of shell pairs
   int64_t nbra = 0, nket = 0;
-  bool solid = false;  // solid-harmonic output (pair lists only)
+  bool solid = false;  // solid-harmonic output
   int64_t work = 0;    // doubles of caller workspace for the H matrices
+  int64_t nentries = 0;      // solid plans: list entries whose H is built (2 per quartet for quartet plans)
   int32_t* d_pl = nullptr;   // per list entry: l of its two shells (bra entries first)
   int32_t* d_pn = nullptr;   // per list entry: contraction lengths
   int64_t* d_hoff = nullptr; // per list entry: where its H matrices start in the workspace
@@ -818,7 +819,7 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
   int ncu = 0, per_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
   const hipError_t oe = p->coul ? plan_coulomb_occupancy(p->lds_bytes, &per_cu)
-                        : p->solid ? plan_solid_occupancy(p->lds_bytes, &per_cu)
+                        : p->solid ? plan_solid_occupancy(p->pairs, p->lds_bytes, &per_cu)
                         : p->pairs ? (p->f32 ? plan_occupancy_f32p(p->lds_bytes, &per_cu)
                                            : plan_occupancy_f64p(p->lds_bytes, &per_cu))
                                  : (p->f32 ? plan_occupancy_f32(p->lds_bytes, &per_cu)
@@ -957,8 +958,8 @@ static eri4_status plan_launch(eri4_plan plan, const Shells& shl, double* work, 
   eri4_status st = ensure_device(&d);
   if (st != ERI4_SUCCESS) return st;
   if (plan->solid)
-    HIP_TRY(solid_hpairs_launch((int)plan->nbra, (int)plan->nket, plan->kmax, stream, plan->d_pl, plan->d_pn, shl,
-                                plan->d_hoff, d->stab, work));
+    HIP_TRY(solid_hpairs_launch(plan->pairs ? plan->nbra : -1, plan->nentries, plan->kmax, stream, plan->d_pl,
+                                plan->d_pn, shl, plan->d_hoff, d->stab, work));
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, plan->d_counter);
   HIP_TRY(hipGetLastError());
   const PlanArgs a{plan->d_classes, plan->d_items, plan->nitems, plan->d_qoff, plan->d_nprim, plan->d_counter, shl,
@@ -966,7 +967,7 @@ static eri4_status plan_launch(eri4_plan plan, const Shells& shl, double* work, 
   const Tables t{d->boys, d->rtab};
   const dim3 grid(plan->grid);
   if (plan->solid)
-    HIP_TRY(plan_solid_launch(grid, plan->lds_bytes, stream, t, a, plan->nbra, plan->d_hoff, work));
+    HIP_TRY(plan_solid_launch(plan->pairs, grid, plan->lds_bytes, stream, t, a, plan->nbra, plan->d_hoff, work));
   else if (plan->pairs)
     HIP_TRY(plan->f32 ? plan_launch_f32p(grid, plan->lds_bytes, stream, t, a)
                       : plan_launch_f64p(grid, plan->lds_bytes, stream, t, a));
@@ -982,7 +983,69 @@ eri4_status eri4_plan_execute(eri4_plan plan, const double* centers, const doubl
   if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
   if (plan->pairs)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan made from pair lists: use eri4_plan_execute_pairs");
+  if (plan->solid) return fail(ERI4_ERROR_INVALID_ARGUMENT, "solid-harmonic plan: use eri4_plan_execute_solid");
   return plan_launch(plan, Shells{centers, exponents, coeffs, nullptr, nullptr, nullptr, 0}, nullptr, 0, out, stream);
+}
+
+// Workspace layout of a solid plan's H matrices: entry e (l and contraction
+// lengths pl[2e..2e+1], pn[2e..2e+1]; a ket pair if e >= nbra, or for nbra < 0
+// if e is odd) holds K1 * K2 slots from hoff[e] (solid_hpairs_kernel); uploads
+// pl, pn and hoff into the plan and sets its workspace size.  Frees the plan
+// and clears *plan on error.
+static eri4_status solid_entries(eri4_plan* plan, int64_t ne, int64_t nbra, const int32_t* pl, const int32_t* pn) {
+  eri4_plan_s* p = *plan;
+  std::vector<int64_t> hoff(ne);
+  int64_t off = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    hoff[e] = off;
+    const int l1 = pl[2 * e], l2 = pl[2 * e + 1];
+    off += (int64_t)pn[2 * e] * pn[2 * e + 1] * solid_pair_units(l1, l2, nbra < 0 ? (e & 1) != 0 : e >= nbra) * 16 *
+           ((nherm(l1 + l2) + 3) & ~3);
+  }
+  p->work = off;
+  p->nentries = ne;
+  const bool ok = hipMalloc(&p->d_pl, std::max<int64_t>(1, 2 * ne) * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(&p->d_pn, std::max<int64_t>(1, 2 * ne) * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(&p->d_hoff, std::max<int64_t>(1, ne) * sizeof(int64_t)) == hipSuccess;
+  hipError_t e = ok ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_pl, pl, 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_pn, pn, 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_hoff, hoff.data(), ne * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    plan_free(p);
+    *plan = nullptr;
+    return ok ? fail(ERI4_ERROR_HIP, "plan upload: %s", hipGetErrorString(e))
+              : fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation for the plan failed");
+  }
+  return ERI4_SUCCESS;
+}
+
+eri4_status eri4_plan_create_solid(eri4_plan* plan, int64_t nquartets, const int32_t* l, const int32_t* nprim,
+                                   int kmax, const char* tune_file) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan pointer");
+  *plan = nullptr;
+  std::vector<eri4_tile_choice> choices;
+  if (tune_file) {
+    const eri4_status st = read_tile_table(tune_file, &choices);
+    if (st != ERI4_SUCCESS) return st;
+  }
+  eri4_status st = plan_create(plan, nquartets, l, nprim, kmax, ERI4_PREC_FP64, choices.data(), (int)choices.size(),
+                               false, 0, 0, true);
+  if (st != ERI4_SUCCESS) return st;
+  // entries 2q (bra pair) and 2q + 1 (ket pair): the quartet arrays as they are
+  return solid_entries(plan, 2 * nquartets, -1, l, nprim);
+}
+
+eri4_status eri4_plan_execute_solid(eri4_plan plan, const double* centers, const double* exponents,
+                                    const double* coeffs, double* work, int64_t work_size, double* out,
+                                    hipStream_t stream) {
+  g_err.clear();
+  if (!plan) return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (plan->pairs) return fail(ERI4_ERROR_INVALID_ARGUMENT, "plan made from pair lists: use eri4_plan_execute_pairs");
+  if (!plan->solid) return fail(ERI4_ERROR_INVALID_ARGUMENT, "Cartesian plan: use eri4_plan_execute");
+  return plan_launch(plan, Shells{centers, exponents, coeffs, nullptr, nullptr, nullptr, 0}, work, work_size, out,
+                     stream);
 }
 
 eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t* bra_l, const int32_t* bra_nprim,
@@ -1015,12 +1078,9 @@ eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t*
     }
   eri4_status st = plan_create(plan, nq, l.data(), np.data(), kmax, precision, choices, nchoices, true, nbra, nket, solid);
   if (st != ERI4_SUCCESS || !solid) return st;
-  // H matrices of every list entry, kmax^2 primitive-pair slots each
-  eri4_plan_s* p = *plan;
+  // H matrices of every list entry, bra entries first
   const int64_t ne = nbra + nket;
   std::vector<int32_t> pl(2 * ne), pn(2 * ne);
-  std::vector<int64_t> hoff(ne);
-  int64_t off = 0;
   for (int64_t e = 0; e < ne; ++e) {
     const bool ket = e >= nbra;
     const int64_t i = ket ? e - nbra : e;
@@ -1028,25 +1088,8 @@ eri4_status eri4_plan_create_pairs(eri4_plan* plan, int64_t nbra, const int32_t*
     const int32_t* nsrc = ket ? ket_nprim : bra_nprim;
     pl[2 * e] = lsrc[2 * i], pl[2 * e + 1] = lsrc[2 * i + 1];
     pn[2 * e] = nsrc[2 * i], pn[2 * e + 1] = nsrc[2 * i + 1];
-    hoff[e] = off;
-    const int l1 = pl[2 * e], l2 = pl[2 * e + 1];
-    off += (int64_t)kmax * kmax * solid_pair_units(l1, l2, ket) * 16 * ((nherm(l1 + l2) + 3) & ~3);
   }
-  p->work = off;
-  const bool ok = hipMalloc(&p->d_pl, std::max<int64_t>(1, 2 * ne) * sizeof(int32_t)) == hipSuccess &&
-                  hipMalloc(&p->d_pn, std::max<int64_t>(1, 2 * ne) * sizeof(int32_t)) == hipSuccess &&
-                  hipMalloc(&p->d_hoff, std::max<int64_t>(1, ne) * sizeof(int64_t)) == hipSuccess;
-  hipError_t e = ok ? hipSuccess : hipErrorOutOfMemory;
-  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_pl, pl.data(), 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_pn, pn.data(), 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess && ne > 0) e = hipMemcpy(p->d_hoff, hoff.data(), ne * sizeof(int64_t), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    plan_free(p);
-    *plan = nullptr;
-    return ok ? fail(ERI4_ERROR_HIP, "plan upload: %s", hipGetErrorString(e))
-              : fail(ERI4_ERROR_OUT_OF_MEMORY, "device allocation for the plan failed");
-  }
-  return ERI4_SUCCESS;
+  return solid_entries(plan, ne, nbra, pl.data(), pn.data());
 }
 
 int64_t eri4_plan_work_size(eri4_plan plan) { return plan ? plan->work : -1; }

@@ -696,7 +696,8 @@ __device__ __forceinline__ void ket_scale(const Lds& s, int kmax, int Ka, int Kb
 // NC1 first-transform column blocks of this wave.
 // SOLID: rows and columns are real solid harmonics and both transforms read
 // their H matrices from hb / hk (this quartet's, hbs / hks doubles per
-// primitive pair, pair (i, j) at slot i * kmax + j); FP64 only.
+// primitive pair, pair (i, j) of shells with K1, K2 primitives at slot
+// i * K2 + j); FP64 only.
 // COUL: no second transform; the first transform's [ab|q] is contracted with
 // the ket density in Hermite space, dket[q] = sum_cd E_cd^q D_cd of ket pair
 // (k, l) at hk + (k * kmax + l) * hks (coulomb_dket_kernel), giving
@@ -827,7 +828,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       // first transform, accumulated over ij: [ab|q] += E_ab^p [p|q]
       if constexpr (NC1 > 0 && SOLID) {
         const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
-        gemm1_h<NR, NC1, SLAB>(acc1, hb + (i * kmax + j) * hbs + (row0 / 16) * (cp.np4 * 16) + lane, s.box, s.ptab,
+        gemm1_h<NR, NC1, SLAB>(acc1, hb + (i * Kb + j) * hbs + (row0 / 16) * (cp.np4 * 16) + lane, s.box, s.ptab,
                                offq, tq, cp.np4, cp.L, cp.S1, lane);
       } else if constexpr (NC1 > 0) {
         gemm1_pair<NR, NC1, SLAB, F32>(acc1, s.brae, s.box, s.ptab, rowx, rowy, rowz, offq, tq, cp.np4, cp.L, cp.S1, lane);
@@ -912,7 +913,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       const bool first = kl == 0;
       if constexpr (SOLID) {
         const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
-        const double* hkp = hk + (k * kmax + l) * hks + lane;
+        const double* hkp = hk + (k * Kd + l) * hks + lane;
         if (ng >= 2 && G2 >= 2)
           gemm2_group_h<NR, 2>(cp, s.X, hkp, cb0, row0, outq, first, lane);
         else

@@ -86,12 +86,13 @@ struct PlanArgs {
   Shells shells;
   double* out;
 };
-// Solid-harmonic pair-list plans (eri4_solid.hip): H of every bra and ket list
-// entry (pl, pn: l and contraction lengths per entry, bra entries first; hoff:
-// where each entry's H starts in h), then the persistent kernel that reads it.
+// Solid-harmonic plans (eri4_solid.hip): H of every list entry (pl, pn: l and
+// contraction lengths per entry; bra entries first for pair-list plans, bra
+// and ket pair of each quartet alternating for quartet plans; hoff: where each
+// entry's H starts in h), then the persistent kernel that reads it.
 hipError_t plan_solid_set_attrs();
-hipError_t plan_solid_occupancy(int lds_bytes, int* per_cu);
-hipError_t plan_solid_launch(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a,
+hipError_t plan_solid_occupancy(bool pairs, int lds_bytes, int* per_cu);
+hipError_t plan_solid_launch(bool pairs, dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a,
                              int64_t nbra, const int64_t* hoff, const double* h);
 hipError_t plan_coulomb_set_attrs();
 hipError_t plan_coulomb_occupancy(int lds_bytes, int* per_cu);
@@ -99,8 +100,10 @@ hipError_t plan_coulomb_launch(dim3 grid, int lds_bytes, hipStream_t s, const Ta
                                int nbra, int kmax, const int32_t* pl, const int32_t* pn, const double* ket_dens,
                                const int64_t* doff, const int64_t* dkoff, const int64_t* joff, double* dket,
                                double* jpart, double* out);
-hipError_t solid_hpairs_launch(int nbra, int nket, int kmax, hipStream_t s, const int32_t* pl, const int32_t* pn,
-                               const Shells& x, const int64_t* hoff, const double* stab, double* h);
+// nbra < 0: the alternating (quartet) form, all entries read from x.centers, ...
+hipError_t solid_hpairs_launch(int64_t nbra, int64_t nentries, int kmax, hipStream_t s, const int32_t* pl,
+                               const int32_t* pn, const Shells& x, const int64_t* hoff, const double* stab,
+                               double* h);
 
 #define ERI4_PLAN_KERNEL_ENTRIES(sfx)                                                                   \
   hipError_t plan_set_attrs_##sfx();                                                                   \

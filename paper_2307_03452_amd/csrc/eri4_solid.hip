@@ -1,6 +1,8 @@
 // eri4_solid.hip -- solid-harmonic output (FP64): the kernel that builds the H
 // matrices of every primitive pair, and the single-class integral kernels that
 // read them, one instance per tile height and R layout.
+#include <algorithm>
+
 #include "eri4_device.h"
 
 namespace eri4 {
@@ -110,10 +112,11 @@ __device__ __forceinline__ void build_h(int l1, int l2, bool ket, const double* 
 }
 
 // Batch form: one workgroup per (quartet q0 + blockIdx.x, side = blockIdx.y & 1,
-// pair slot blockIdx.y >> 1 = i * kmax + j); side 0 is the bra (shells a, b;
-// cp.nrt * cp.rb units, cp.np4 k), side 1 the ket (shells c, d; cp.ncdb units,
-// cp.nq4 k).  H of quartet q0 + x, slot s at hbra + (x * kmax^2 + s) * hbs (bra)
-// or hket + (x * kmax^2 + s) * hks (ket).
+// primitive pair (i, j) = divmod(blockIdx.y >> 1, kmax)); side 0 is the bra
+// (shells a, b; cp.nrt * cp.rb units, cp.np4 k), side 1 the ket (shells c, d;
+// cp.ncdb units, cp.nq4 k).  Quartet q0 + x reserves kmax^2 slots per side and
+// fills the first K1 * K2: pair (i, j) at slot i * K2 + j, i.e. at hbra +
+// (x * kmax^2 + i * K2 + j) * hbs (bra) or the same in hket with hks (ket).
 __global__ __launch_bounds__(kThreads, 1) void solid_h_kernel(
     const ClassParams cp, const double* __restrict__ centers, const double* __restrict__ exps,
     const double* __restrict__ coefs, const int32_t* __restrict__ nprim, const double* __restrict__ stab,
@@ -129,41 +132,53 @@ __global__ __launch_bounds__(kThreads, 1) void solid_h_kernel(
   if (K1 < 1 || K1 > kmax || K2 < 1 || K2 > kmax || i >= K1 || j >= K2) return;
   const double* e = exps + (q * 4 + 2 * side) * kmax;
   const double* w = coefs + (q * 4 + 2 * side) * kmax;
-  double* H = side ? hket + (iq * kmax * kmax + slot) * hks : hbra + (iq * kmax * kmax + slot) * hbs;
+  const int64_t at = iq * kmax * kmax + i * K2 + j;
+  double* H = side ? hket + at * hks : hbra + at * hbs;
   build_h(side ? cp.lc : cp.la, side ? cp.ld : cp.lb, side == 1, centers + q * 12 + 6 * side, e[i], e[kmax + j], w[i],
           w[kmax + j], stab, H, side ? cp.ncdb : cp.nrt * cp.rb, side ? cp.nq4 : cp.np4, (double*)dyn, tid);
 }
 
-// List form: one workgroup per (list entry blockIdx.x, slot blockIdx.y = i * kmax
-// + j); entries 0..nbra-1 are the bra list, then the ket list.  An entry's H
-// starts at h + hoff[entry], kmax^2 slots of solid_pair_units(...) * 16 * nk4
-// doubles; bra rows are padded to 64 so that every tile height can read them.
+// List form: one workgroup per (list entry e0 + blockIdx.x, primitive pair (i, j) =
+// divmod(blockIdx.y, kmax)).  With nbra >= 0, entries 0..nbra-1 are the bra
+// list (shells from bcenters, ...) and the rest the ket list (kcenters, ...);
+// with nbra < 0 the entries alternate, 2q the bra pair and 2q + 1 the ket pair
+// of quartet q, all read from bcenters, ... at the entry's own index (the
+// quartet layout seen as a list of pairs).  An entry with K1 * K2 primitive
+// pairs holds K1 * K2 slots from h + hoff[entry], pair (i, j) at slot i * K2 +
+// j, each solid_pair_units(...) * 16 * nk4 doubles; bra rows are padded to 64
+// so that every tile height can read them.
 __global__ __launch_bounds__(kThreads, 1) void solid_hpairs_kernel(
-    int nbra, int kmax, const int32_t* __restrict__ pl, const int32_t* __restrict__ pn,
+    int64_t e0, int64_t nbra, int kmax, const int32_t* __restrict__ pl, const int32_t* __restrict__ pn,
     const double* __restrict__ bcenters, const double* __restrict__ bexps, const double* __restrict__ bcoefs,
     const double* __restrict__ kcenters, const double* __restrict__ kexps, const double* __restrict__ kcoefs,
     const int64_t* __restrict__ hoff, const double* __restrict__ stab, double* __restrict__ h) {
   extern __shared__ __align__(16) unsigned char dyn[];
   const int tid = threadIdx.x;
-  const int p = blockIdx.x, slot = blockIdx.y;
+  const int64_t p = e0 + blockIdx.x;
+  const int slot = blockIdx.y;
   const int i = slot / kmax, j = slot - (slot / kmax) * kmax;
   const int K1 = pn[2 * p], K2 = pn[2 * p + 1];
   if (K1 < 1 || K1 > kmax || K2 < 1 || K2 > kmax || i >= K1 || j >= K2) return;
-  const bool ket = p >= nbra;
-  const int64_t ip = ket ? p - nbra : p;
+  const bool alt = nbra < 0;
+  const bool ket = alt ? (p & 1) != 0 : p >= nbra;
+  const bool klist = ket && !alt;
+  const int64_t ip = klist ? p - nbra : p;
   const int l1 = pl[2 * p], l2 = pl[2 * p + 1];
-  const double* e = (ket ? kexps : bexps) + ip * 2 * kmax;
-  const double* w = (ket ? kcoefs : bcoefs) + ip * 2 * kmax;
+  const double* e = (klist ? kexps : bexps) + ip * 2 * kmax;
+  const double* w = (klist ? kcoefs : bcoefs) + ip * 2 * kmax;
   const int nk4 = (nherm(l1 + l2) + 3) & ~3;
   const int nunits = solid_pair_units(l1, l2, ket);
-  build_h(l1, l2, ket, (ket ? kcenters : bcenters) + ip * 6, e[i], e[kmax + j], w[i], w[kmax + j], stab,
-          h + hoff[p] + (int64_t)slot * nunits * 16 * nk4, nunits, nk4, (double*)dyn, tid);
+  build_h(l1, l2, ket, (klist ? kcenters : bcenters) + ip * 6, e[i], e[kmax + j], w[i], w[kmax + j], stab,
+          h + hoff[p] + (int64_t)(i * K2 + j) * nunits * 16 * nk4, nunits, nk4, (double*)dyn, tid);
 }
 
-// Persistent kernel of a solid-harmonic pair-list plan: the work loop of
-// eri4_plan_kernel (shells from the bra and ket lists), both transforms reading
-// the H matrices of the quartet's bra entry (h + hoff[q / nket]) and ket entry
-// (h + hoff[nbra + q % nket]) built by solid_hpairs_kernel.
+// Persistent kernel of a solid-harmonic plan: the work loop of
+// eri4_plan_kernel, both transforms reading the H matrices built by
+// solid_hpairs_kernel.  PAIRS: shells from the bra and ket lists, H of the
+// quartet's bra entry at h + hoff[q / nket] and of its ket entry at h +
+// hoff[nbra + q % nket]; otherwise shells from the quartet arrays and H at h +
+// hoff[2q] (bra) and h + hoff[2q + 1] (ket).
+template <bool PAIRS>
 __global__ __launch_bounds__(kThreads, 1) void eri4_plan_solid_kernel(
     const ClassParams* __restrict__ classes, const int2* __restrict__ items, int nitems,
     const int64_t* __restrict__ qoff, const int32_t* __restrict__ nprim, int* __restrict__ counter,
@@ -188,13 +203,20 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_plan_solid_kernel(
     const int rt = rc & 0xffff;
     const uint2* rt_L = rtab + cp.rtab_off;
     double* oq = out + qoff[q];
-    const int64_t ib = q / nket, ik = q - ib * nket;
-    const double* hb = h + hoff[ib];
-    const double* hk = h + hoff[nbra + ik];
+    const double* hb;
+    const double* hk;
+    if constexpr (PAIRS) {
+      const int64_t ib = q / nket, ik = q - ib * nket;
+      hb = h + hoff[ib];
+      hk = h + hoff[nbra + ik];
+    } else {
+      hb = h + hoff[2 * (int64_t)q];
+      hk = h + hoff[2 * (int64_t)q + 1];
+    }
     const int64_t hbs = (int64_t)solid_pair_units(cp.la, cp.lb, false) * 16 * cp.np4;
     const int64_t hks = (int64_t)cp.ncdb * 16 * cp.nq4;
 #define T(RB, LAY)                                                                                                   \
-  process_tile<RB, LAY, false, true, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, \
+  process_tile<RB, LAY, false, PAIRS, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, wave, \
                                            lane, kcenters, kexps, kcoefs, nket, hb, hk, hbs, hks)
     const int lay = cp.lay;
     if (lay == kLaySlab) {
@@ -211,30 +233,46 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_plan_solid_kernel(
 }  // namespace
 
 hipError_t plan_solid_set_attrs() {
-  return hipFuncSetAttribute((const void*)eri4_plan_solid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)eri4_plan_solid_kernel<true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes - 64);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)eri4_plan_solid_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              kMaxLdsBytes - 64);
 }
 
-hipError_t plan_solid_occupancy(int lds_bytes, int* per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void*)eri4_plan_solid_kernel, kThreads,
-                                                      lds_bytes);
+hipError_t plan_solid_occupancy(bool pairs, int lds_bytes, int* per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      per_cu, pairs ? (const void*)eri4_plan_solid_kernel<true> : (const void*)eri4_plan_solid_kernel<false>, kThreads,
+      lds_bytes);
 }
 
-hipError_t plan_solid_launch(dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a,
+hipError_t plan_solid_launch(bool pairs, dim3 grid, int lds_bytes, hipStream_t s, const Tables& t, const PlanArgs& a,
                              int64_t nbra, const int64_t* hoff, const double* h) {
   const Shells& x = a.shells;
-  hipLaunchKernelGGL(eri4_plan_solid_kernel, grid, dim3(kThreads), lds_bytes, s, a.classes, a.items, a.nitems, a.qoff,
-                     a.nprim, a.counter, t.boys, t.rtab, x.centers, x.exps, x.coefs, a.out, x.kcenters, x.kexps,
-                     x.kcoefs, x.nket, nbra, hoff, h);
+  if (pairs)
+    hipLaunchKernelGGL(eri4_plan_solid_kernel<true>, grid, dim3(kThreads), lds_bytes, s, a.classes, a.items, a.nitems,
+                       a.qoff, a.nprim, a.counter, t.boys, t.rtab, x.centers, x.exps, x.coefs, a.out, x.kcenters,
+                       x.kexps, x.kcoefs, x.nket, nbra, hoff, h);
+  else
+    hipLaunchKernelGGL(eri4_plan_solid_kernel<false>, grid, dim3(kThreads), lds_bytes, s, a.classes, a.items,
+                       a.nitems, a.qoff, a.nprim, a.counter, t.boys, t.rtab, x.centers, x.exps, x.coefs, a.out,
+                       nullptr, nullptr, nullptr, (int64_t)0, (int64_t)0, hoff, h);
   return hipGetLastError();
 }
 
-hipError_t solid_hpairs_launch(int nbra, int nket, int kmax, hipStream_t s, const int32_t* pl, const int32_t* pn,
-                               const Shells& x, const int64_t* hoff, const double* stab, double* h) {
-  const dim3 grid((unsigned)(nbra + nket), (unsigned)(kmax * kmax));
-  hipLaunchKernelGGL(solid_hpairs_kernel, grid, dim3(kThreads), kSolidHLds, s, nbra, kmax, pl, pn, x.centers, x.exps,
-                     x.coefs, x.kcenters, x.kexps, x.kcoefs, hoff, stab, h);
-  return hipGetLastError();
+hipError_t solid_hpairs_launch(int64_t nbra, int64_t nentries, int kmax, hipStream_t s, const int32_t* pl,
+                               const int32_t* pn, const Shells& x, const int64_t* hoff, const double* stab,
+                               double* h) {
+  // entries per launch: the grid's x extent in work-items stays below 2^32
+  constexpr int64_t kChunk = (int64_t)1 << 22;
+  for (int64_t e0 = 0; e0 < nentries; e0 += kChunk) {
+    const dim3 grid((unsigned)std::min(kChunk, nentries - e0), (unsigned)(kmax * kmax));
+    hipLaunchKernelGGL(solid_hpairs_kernel, grid, dim3(kThreads), kSolidHLds, s, e0, nbra, kmax, pl, pn, x.centers,
+                       x.exps, x.coefs, x.kcenters, x.kexps, x.kcoefs, hoff, stab, h);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t solid_set_attrs() {

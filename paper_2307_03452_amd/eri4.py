@@ -72,7 +72,7 @@ EXPORTS = ("eri4_ncart", "eri4_quartet_size", "eri4_last_error", "eri4_version",
            "eri4_boys", "eri4_hermite_r", "eri4_hermite_e", "eri4_solid_coefficients", "eri4_solid_work_size",
            "eri4_batch_solid", "eri4_coulomb_work_size", "eri4_batch_coulomb", "eri4_exchange_work_size",
            "eri4_batch_exchange", "eri4_static_scratch_bytes",
-           "eri4_batch_coulomb_static")
+           "eri4_batch_coulomb_static", "eri4_plan_create_solid", "eri4_plan_execute_solid")
 
 _lib = None
 
@@ -144,6 +144,10 @@ def lib() -> ctypes.CDLL:
         L.eri4_plan_work_size.restype = i64
         L.eri4_plan_execute_pairs.argtypes = [vp] * 7 + [vp, i64, vp, vp]
         L.eri4_plan_execute_pairs.restype = c_int
+        L.eri4_plan_create_solid.argtypes = [ctypes.POINTER(vp), i64, vp, vp, c_int, ctypes.c_char_p]
+        L.eri4_plan_create_solid.restype = c_int
+        L.eri4_plan_execute_solid.argtypes = [vp] * 5 + [i64, vp, vp]
+        L.eri4_plan_execute_solid.restype = c_int
         L.eri4_boys.argtypes = [c_int, i64, vp, vp, vp]
         L.eri4_boys.restype = c_int
         L.eri4_hermite_r.argtypes = [c_int, i64, vp, vp, vp, vp, vp, vp]
@@ -444,6 +448,51 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+class SolidPlan(Plan):
+    """A mixed-class batch over real solid harmonics (eri4_plan_*_solid): host
+    int32 arrays lq, nprim [nq, 4] as Plan, FP64 transforms, an optional tile
+    table file.  execute() takes the device arrays of Plan.execute and a
+    float64 device workspace of work_size doubles (allocated if not given);
+    quartet q's [2la+1][2lb+1][2lc+1][2ld+1] block starts at offsets()[q]."""
+
+    def __init__(self, lq, nprim, kmax: int, tune_file=None):
+        import numpy as np
+        self._lq = np.ascontiguousarray(lq, dtype=np.int32)
+        self._np = np.ascontiguousarray(nprim, dtype=np.int32)
+        assert self._lq.shape == self._np.shape and self._lq.ndim == 2 and self._lq.shape[1] == 4
+        self.nq = self._lq.shape[0]
+        self.kmax = int(kmax)
+        self.precision = "fp64"
+        h = ctypes.c_void_p()
+        _check(lib().eri4_plan_create_solid(
+            ctypes.byref(h), self.nq, self._lq.ctypes.data_as(ctypes.c_void_p),
+            self._np.ctypes.data_as(ctypes.c_void_p), self.kmax,
+            str(tune_file).encode() if tune_file is not None else None))
+        self._h = h
+
+    @property
+    def work_size(self) -> int:
+        return lib().eri4_plan_work_size(self._h)
+
+    def execute(self, centers, exps, coefs, out=None, work=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.output_size, dtype=torch.float64, device=centers.device)
+        if work is None:
+            work = torch.empty(max(1, self.work_size), dtype=torch.float64, device=centers.device)
+        if out.numel() < self.output_size:
+            raise ValueError("output buffer too small")
+        if work.numel() < self.work_size:
+            raise ValueError("workspace too small")
+        if (tuple(centers.shape) != (self.nq, 4, 3) or tuple(exps.shape) != (self.nq, 4, self.kmax)
+                or tuple(coefs.shape) != (self.nq, 4, self.kmax)):
+            raise ValueError("inputs do not match the plan")
+        _check(lib().eri4_plan_execute_solid(
+            self._h, _ptr(centers, "float64"), _ptr(exps, "float64"), _ptr(coefs, "float64"),
+            _ptr(work, "float64"), work.numel(), _ptr(out, "float64"), _stream(stream)))
+        return out
 
 
 class PairPlan(Plan):

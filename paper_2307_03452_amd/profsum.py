@@ -63,6 +63,9 @@ def source_hash(files):
 
 def trace(a):
     rows = [r for r in _rows(a.csv) if _match(r, a.kernel, a.grid)]
+    if a.select:
+        i0, i1 = (int(x) for x in a.select.split(":"))
+        rows = rows[i0:i1]
     if not rows:
         sys.exit(f"no dispatch of {a.kernel} with grid {a.grid} in {a.csv}")
     durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
@@ -87,6 +90,8 @@ def trace(a):
             "LDS excludes the dynamic allocation)", "",
             "| dispatch | duration ns |", "|---|---|"]
     out += [f"| {r['Dispatch_Id']} | {d} |" for r, d in zip(rows, durs)]
+    if a.select:
+        out += ["", f"(matching dispatches {a.select} in trace order)"]
     out += ["", f"{len(rows)} dispatches; mean {mean_all:.0f} ns over all, min {min(durs)} ns, max {max(durs)} ns; "
                 f"mean {mean:.0f} ns over the {len(timed)} after the first {a.skip_first} (warm-up)."]
     if others:
@@ -151,6 +156,8 @@ def main(argv=None):
     t.add_argument("--grid", type=int)
     t.add_argument("--flops", type=float)
     t.add_argument("--skip-first", type=int, default=1, help="warm-up dispatches left out of the timed mean")
+    t.add_argument("--select", help="START:STOP, keep only these matching dispatches (in trace order), e.g. one "
+                                    "case of a run that launches the same kernel and grid for several cases")
     t.add_argument("--title", default="")
     t.add_argument("--command", default="")
     t.add_argument("--sources", nargs="*", default=[])
