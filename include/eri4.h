@@ -156,11 +156,16 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets,
  * matrix elements directly from [q|ab) as the way around the transposes between
  * its transforms (Sec. 3).  Here the ket density is taken to Hermite space per
  * ket primitive pair, dket_q = sum_cd E_cd^q D_cd (sign of eq. (pq) included),
- * and contracted with [ab|q] from the first transform; the second transform and
- * the N_ab N_cd output are never formed.  FP64, Cartesian functions.
+ * and carried through the Hermite integrals before the bra transform (eqs.
+ * (abcd_to_hermite), (pq) associated the other way): per bra primitive pair,
+ * w_p = sum over ket pairs of sum_q [p+q] dket_q (a matrix-vector product per
+ * primitive quartet), then J_ab = sum_p E_ab^p w_p, summed over the bra
+ * primitive pairs in a fixed order.  Neither [ab|q] nor the N_ab N_cd
+ * integrals are formed.  FP64, Cartesian functions.
  *   dens  device double [nquartets][Nc][Nd]   (the caller gathers each quartet's block)
  *   out   device double [nquartets][Na][Nb]   J contributions, quartets in input order
- *   work  device double [work_size], caller-owned scratch for dket
+ *   work  device double [work_size], caller-owned scratch for dket and the
+ *         J of each bra primitive pair
  * Other arguments as eri4_batch; quartets run in passes of as many as the
  * workspace holds (eri4_coulomb_work_size(la, lb, lc, ld, kmax, n) doubles for
  * n quartets, -1 for bad arguments).  Symmetry (the (cd|ab) contribution, or
@@ -200,7 +205,7 @@ eri4_status eri4_batch_exchange(int la, int lb, int lc, int ld, int64_t nquartet
  * eri4_batch_coulomb without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  It calls no hipMalloc, hipFree or other
- * allocating routine: the Hermite-space densities live in a static device
+ * allocating routine: the Hermite-space densities and the per-bra-pair J live in a static device
  * array of eri4_static_scratch_bytes() bytes (32 MiB) that the library holds
  * on each device until the process ends.  Quartets run in passes of as many
  * as that array holds; a class whose single quartet would need more is
@@ -382,9 +387,10 @@ eri4_status eri4_plan_execute_pairs(eri4_plan plan, const double* bra_centers, c
  * bra entry i,
  *   J_i[ab] = sum_j sum_cd (ab|cd)_ij D_j[cd]
  * with D_j the density block of ket entry j.  dket of each ket entry is built
- * once per execute and shared by every bra entry; each quartet's J rows go to
- * the workspace and are summed over j in a fixed order (reproducible bits).
- * FP64, Cartesian; the library picks the tiles.
+ * once per execute and shared by every bra entry; each quartet's J rows
+ * (computed as in eri4_batch_coulomb, all its bra primitive pairs in one
+ * workgroup) go to the workspace and are summed over j in a fixed order
+ * (reproducible bits).  FP64, Cartesian.
  * eri4_plan_create_coulomb: host arrays as eri4_plan_create_pairs.
  * eri4_plan_execute_coulomb: lists as eri4_plan_execute_pairs, and
  *   ket_dens  device double, the blocks D_j[Nc][Nd] of the ket entries one after

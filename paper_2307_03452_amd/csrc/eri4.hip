@@ -460,45 +460,83 @@ eri4_status eri4_batch_solid(int la, int lb, int lc, int ld, int64_t nquartets, 
   return ERI4_SUCCESS;
 }
 
-// The Coulomb kernels hold kCoulLds doubles of static LDS beside the dynamic area.
+// Parameters and LDS layout of the Coulomb (J-engine) kernels: the R box of
+// the first layout that fits (two boxes up to L = kBox2LMax, one box up to
+// kBoxLMax, else slab), the bra tables, and the w buffer (inside the R box when
+// that is large enough: w is written after the last recursion of a bra pair).
+// No [ab|q] tile and no ket tables.
+bool jengine_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* out) {
+  const int L = la + lb + lc + ld;
+  if (L > kMaxL) return false;
+  static const int order[3] = {kLayBox2, kLayBox, kLaySlab};
+  for (int lay : order) {
+    const bool slab = lay == kLaySlab, two = lay == kLayBox2;
+    if ((two && L > kBox2LMax) || (lay == kLayBox && L > kBoxLMax)) continue;
+    ClassParams p = make_params(la, lb, lc, ld, kmax, 1, slab, two);
+    const int box_b = r_cells(slab, L) * 8;
+    p.o_brae = p.o_union + align16(box_b);
+    p.o_box1 = p.o_brae + align16(3 * p.tbaxis * 8);
+    int end = p.o_box1 + (two ? align16(box_b) : 0);
+    if (box_b >= kJw * 8) {
+      p.o_jw = p.o_union;
+    } else {
+      p.o_jw = end;
+      end += kJw * 8;
+    }
+    p.o_kete = p.o_union;  // unused
+    p.lds_bytes = end;
+    p.nrt = 1;
+    if (p.lds_bytes > kMaxLdsBytes - 64) continue;
+    p.rtab_off = d ? d->rstart[(slab ? 1 : 0) * (kMaxL + 1) + L] : 0;
+    *out = p;
+    return true;
+  }
+  return false;
+}
+
+// ds: doubles of one ket primitive pair's dket; ps: of one bra pair's J^ij.
 static bool coulomb_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* p,
-                           int64_t* ds) {
-  if (!pick_params(la, lb, lc, ld, kmax, d, kMaxLdsBytes - kCoulLds * 8 - 512, p)) return false;
+                           int64_t* ds, int64_t* ps) {
+  if (!jengine_params(la, lb, lc, ld, kmax, d, p)) return false;
   *ds = 16 * (int64_t)p->nqb;
+  *ps = p->nab;
   return true;
 }
 
 int64_t eri4_coulomb_work_size(int la, int lb, int lc, int ld, int kmax, int64_t nquartets) {
   if (check_class(la, lb, lc, ld, nquartets, kmax) != ERI4_SUCCESS) return -1;
   ClassParams p;
-  int64_t ds;
-  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds)) return -1;
-  return nquartets * kmax * kmax * ds;
+  int64_t ds, ps;
+  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds, &ps)) return -1;
+  return nquartets * kmax * kmax * (ds + ps);
 }
 
 // J for nquartets quartets in passes of as many as the workspace (work_size
-// doubles) holds the Hermite-space densities of: per pass, the density kernel,
-// then the integral kernel.  Arguments already checked; d is initialised.
+// doubles) holds the Hermite-space densities and per-bra-pair J of: per pass,
+// the density kernel, the J-engine kernel and the sum over bra pairs.
+// Arguments already checked; d is initialised.
 static eri4_status coulomb_passes(int la, int lb, int lc, int ld, int64_t nquartets, const double* centers,
                                   const double* exponents, const double* coeffs, const int32_t* nprim, int kmax,
                                   const double* dens, double* work, int64_t work_size, double* out,
                                   hipStream_t stream, const DeviceState* d) {
   ClassParams p;
-  int64_t ds;
-  if (!coulomb_params(la, lb, lc, ld, kmax, d, &p, &ds))
+  int64_t ds, ps;
+  if (!coulomb_params(la, lb, lc, ld, kmax, d, &p, &ds, &ps))
     return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
-  const int64_t perq = (int64_t)kmax * kmax * ds;
+  const int64_t kk2 = (int64_t)kmax * kmax;
+  const int64_t perq = kk2 * (ds + ps);
   int64_t chunk = work_size / perq;
   if (chunk < 1)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below one quartet's %lld",
                 (long long)work_size, (long long)perq);
-  chunk = std::min<int64_t>(chunk, std::min<int64_t>(((int64_t)1 << 30) / p.nrt, INT32_MAX));
+  chunk = std::min<int64_t>(chunk, ((int64_t)1 << 22) / kk2);  // grid of chunk * kmax^2 workgroups
   for (int64_t q0 = 0; q0 < nquartets; q0 += chunk) {
     const int64_t nq = std::min(chunk, nquartets - q0);
+    double* part = work + nq * kk2 * ds;
     hipError_t e = coulomb_dket_launch(p, nq, stream, centers, exponents, coeffs, nprim, dens, work, q0, ds);
     if (e == hipSuccess)
-      e = coulomb_launch(p, dim3((unsigned)(nq * p.nrt)), stream, Tables{d->boys, d->rtab}, centers, exponents,
-                         coeffs, nprim, out, q0, work, ds);
+      e = coulomb_launch(p, nq, stream, Tables{d->boys, d->rtab}, centers, exponents, coeffs, nprim, part, out, q0,
+                         work, ds);
     if (e != hipSuccess) return fail(ERI4_ERROR_HIP, "kernel launch: %s", hipGetErrorString(e));
   }
   return ERI4_SUCCESS;
@@ -514,12 +552,12 @@ eri4_status eri4_batch_coulomb(int la, int lb, int lc, int ld, int64_t nquartets
   if (!centers || !exponents || !coeffs || !nprim || !dens || !out || !work)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
   ClassParams p;
-  int64_t ds;
-  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds))
+  int64_t ds, ps;
+  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds, &ps))
     return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
-  if (work_size < (int64_t)kmax * kmax * ds)
+  if (work_size < (int64_t)kmax * kmax * (ds + ps))
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "workspace of %lld doubles is below one quartet's %lld",
-                (long long)work_size, (long long)kmax * kmax * ds);
+                (long long)work_size, (long long)kmax * kmax * (ds + ps));
   DeviceState* d;
   st = ensure_device(&d);
   if (st != ERI4_SUCCESS) return st;
@@ -596,12 +634,13 @@ eri4_status eri4_batch_coulomb_static(int la, int lb, int lc, int ld, int64_t nq
   if (!centers || !exponents || !coeffs || !nprim || !dens || !out)
     return fail(ERI4_ERROR_INVALID_ARGUMENT, "NULL buffer pointer");
   ClassParams p;
-  int64_t ds;
-  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds))
+  int64_t ds, ps;
+  if (!coulomb_params(la, lb, lc, ld, kmax, nullptr, &p, &ds, &ps))
     return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", la, lb, lc, ld);
-  if ((int64_t)kmax * kmax * ds > kStaticScratchDoubles)
-    return fail(ERI4_ERROR_UNSUPPORTED, "one quartet's Hermite-space densities (%lld doubles) exceed the %lld-double "
-                "static scratch", (long long)kmax * kmax * ds, (long long)kStaticScratchDoubles);
+  if ((int64_t)kmax * kmax * (ds + ps) > kStaticScratchDoubles)
+    return fail(ERI4_ERROR_UNSUPPORTED, "one quartet's Hermite-space densities and partial J (%lld doubles) exceed "
+                "the %lld-double static scratch", (long long)kmax * kmax * (ds + ps),
+                (long long)kStaticScratchDoubles);
   // no initialisation here: that allocates the tables (eri4_init must have run)
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -735,7 +774,7 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
   p->solid = solid;
   p->coul = coul;
   // dynamic LDS available next to the persistent kernel's static LDS
-  const int limit = coul ? kMaxLdsBytes - kCoulLds * 8 - 512 : kMaxLdsBytes - 64;
+  const int limit = kMaxLdsBytes - 64;
 
   // groups of quartets with the same class and tile choice (the first matching
   // entry of the table, or none), keyed by class * (nchoices + 1) + entry + 1
@@ -767,7 +806,12 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
   std::vector<ClassParams> cps(keys.size());
   for (size_t c = 0; c < keys.size(); ++c) {
     const auto& k = keys[c];
-    if (k[4] >= 0) {
+    if (coul) {
+      if (!jengine_params(k[0], k[1], k[2], k[3], kmax, d, &cps[c])) {
+        plan_free(p);
+        return fail(ERI4_ERROR_UNSUPPORTED, "class (%d %d|%d %d) does not fit in LDS", k[0], k[1], k[2], k[3]);
+      }
+    } else if (k[4] >= 0) {
       const eri4_tile_choice& ch = choices[k[4]];
       if (!try_params(k[0], k[1], k[2], k[3], kmax, ch.rows16, ch.layout, d, limit, &cps[c])) {
         plan_free(p);
@@ -794,6 +838,14 @@ static eri4_status plan_create(eri4_plan* plan, int64_t nquartets, const int32_t
     p->qoff[q] = off;
     off += coul ? (int64_t)c.nab : (int64_t)c.nab * c.ncd;  // Coulomb plans: J rows per quartet
     const double kb = (double)nprim[4 * q] * nprim[4 * q + 1], kk = (double)nprim[4 * q + 2] * nprim[4 * q + 3];
+    if (coul) {
+      // one item per quartet (J-engine): per primitive quartet the recursion
+      // and the matrix-vector product, per bra pair the bra transform
+      cost.push_back(kb * kk * (8000.0 + 4.0 * nherm(c.L) + (double)c.np * c.nq / 128.0) +
+                     kb * (double)c.nab * c.np / 256.0 + 4000.0);
+      items.push_back(make_int2((int)q, qcls[q] << 16));
+      continue;
+    }
     for (int rt = 0; rt < c.nrt; ++rt) {
       const int rows = 16 * std::min(c.rb, (c.nab - rt * c.rb * 16 + 15) / 16);
       // MFMA cycles of the two transforms at 128 FLOP/clk per CU, plus a

@@ -1,8 +1,12 @@
 // eri4_coulomb.hip -- Coulomb contraction without forming (ab|cd) (FP64,
 // Cartesian): J_ab = sum_cd (ab|cd) D_cd per quartet.  The ket density is first
 // taken to Hermite space per ket primitive pair, dket^kl_q = sum_cd E_cd^q D_cd
-// (sign of eq. (pq) included), then the tile code contracts the first
-// transform's [ab|q] with it instead of running the second transform.
+// (sign of eq. (pq) included).  Since (ab|cd) = sum_pq E_ab^p [p+q] E_cd^q
+// (eqs. (abcd_to_hermite), (pq)), J_ab = sum_p E_ab^p w_p with
+// w_p = sum_kl sum_q [p+q]^kl dket^kl_q: the density is carried through the
+// Hermite integrals as a matrix-vector product per primitive quartet, and the
+// bra transform is a matrix-vector product per bra primitive pair, instead of
+// the matrix-matrix products that form [ab|q] (a J-engine).
 #include "eri4_device.h"
 
 namespace eri4 {
@@ -92,40 +96,268 @@ __global__ __launch_bounds__(kThreads, 1) void coulomb_dket_pairs_kernel(
              dket + dkoff[jk] + (int64_t)slot * ds, tid);
 }
 
-// One workgroup = one quartet x one tile of RB*16 bra rows (eri4_fused_kernel
-// with the Coulomb contraction); out: J [nq][Na][Nb].
-template <int RB, int LAY>
+// Hermite-space J of bra primitive pairs ij0..ij1-1 of the quartet whose
+// shells are in s.sh (contraction lengths Ka..Kd), summed over them into
+// outJ[ab] (nab doubles, plain stores).  For each bra pair ij:
+//   w_p  = sum over ket pairs kl, sum_q [p+q]^(0) dket^kl_q
+//   J_ab += sum_p E_ab^p w_p
+// with dket^kl at dket + (k * kmax + l) * ds (coulomb_dket_kernel).  The
+// matrix-vector product runs with thread p on row p; when the bra has at most
+// 256 Hermite functions, G groups of waves take every G-th q and their partial
+// w are added in a fixed order.  The bra transform runs with thread ab on row
+// ab, over p in the Hermite table's (t, u, v) order, the z factors of the row
+// in registers.  NPT: Hermite functions per thread (2 when np > 512).
+// Called by all threads; ends with a barrier.
+constexpr int kJV = 2 * kTableLMax + 1;  // longest v run of a bra Hermite table
+constexpr int kJAb = (ncart(kTableLMax) * ncart(kTableLMax) + kThreads - 1) / kThreads;  // J rows per thread
+
+template <int LAY, int NPT>
+__device__ void jengine_body(const ClassParams& cp, const Lds& s, double* __restrict__ wb,
+                             const double* __restrict__ boys_tab,
+                             const uint2 (&rent)[LAY == kLaySlab ? kRPerThread : kRPerBox], int Ka, int Kb, int Kc,
+                             int Kd, int ij0, int ij1, const double* __restrict__ dket, int64_t ds,
+                             double* __restrict__ outJ, int tid, int wave, int lane) {
+  constexpr bool SLAB = LAY == kLaySlab;
+  const int kmax = cp.kmax, np = cp.np, nq = cp.nq, L = cp.L, S1 = cp.S1, Lb = cp.Lb;
+  const double* A = s.sh;
+  const double* B = s.sh + 3;
+  const double* C = s.sh + 6;
+  const double* D = s.sh + 9;
+  const double* ex = s.sh + 12;
+  const double* co = s.sh + 12 + 4 * kmax;
+  // matrix-vector rows of this thread: group g of G, rows pbase + lane (+ 512)
+  const int P64 = NPT == 1 ? (np + 63) >> 6 : kWaves;
+  const int G = NPT == 1 ? kWaves / P64 : 1;
+  const int g = wave / P64;
+  const int pbase = (wave - g * P64) * 64;
+  const int gstride = P64 * 64;
+  int pidx[NPT];
+  int2 pt[NPT];
+  bool pv[NPT];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    pidx[r] = pbase + lane + r * kThreads;
+    pv[r] = g < G && pidx[r] < np;
+    pt[r] = pv[r] ? s.ptab[pidx[r]] : make_int2(0, 0);
+  }
+  // J rows of this thread and their 1-d table rows
+  int rx[kJAb], ry[kJAb], rz[kJAb];
+  bool av[kJAb];
+#pragma unroll
+  for (int r = 0; r < kJAb; ++r) {
+    const int ab = tid + r * kThreads;
+    av[r] = ab < cp.nab;
+    rx[r] = ry[r] = rz[r] = 0;
+    if (av[r]) {
+      const int ia = ab / cp.nb, ib = ab - (ab / cp.nb) * cp.nb;
+      int ax, ay, az, bx, by, bz;
+      cart_of(cp.la, ia, ax, ay, az);
+      cart_of(cp.lb, ib, bx, by, bz);
+      rx[r] = (ax * (cp.lb + 1) + bx) * cp.tbrow;
+      ry[r] = cp.tbaxis + (ay * (cp.lb + 1) + by) * cp.tbrow;
+      rz[r] = 2 * cp.tbaxis + (az * (cp.lb + 1) + bz) * cp.tbrow;
+    }
+  }
+  double J[kJAb];
+#pragma unroll
+  for (int r = 0; r < kJAb; ++r) J[r] = 0.0;
+
+  for (int ij = ij0; ij < ij1; ++ij) {
+    if (tid == 64) {
+      const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
+      make_pair(s.bpair, ex[i], ex[kmax + j], co[i], co[kmax + j], A, B);
+    }
+    __syncthreads();
+    if (wave == 1)
+      build_etab(s.brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / s.bpair[0], s.bpair + 5, s.bpair + 8, false, lane);
+    double w[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) w[r] = 0.0;
+    for (int kl = 0; kl < Kc * Kd; ++kl) {
+      const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
+      if (tid == 0) {
+        make_pair(s.kpair, ex[2 * kmax + k], ex[3 * kmax + l], co[2 * kmax + k], co[3 * kmax + l], C, D);
+        s.kpair[11] = 1.0;
+      }
+      __syncthreads();
+      if (wave == 0) hermite_base(s, L, boys_tab, lane);
+      __syncthreads();
+      if constexpr (LAY == kLayBox2)
+        hermite_r_lds2(s.box, s.box1, s.baseM, L, s.pqv, rent, tid);
+      else
+        hermite_r_lds(s.box, s.baseM, L, s.pqv, rent, tid);
+      // w_p += sum_q [p+q] dket_q (the sign of eq. (pq) is in dket)
+      const double* __restrict__ dq = dket + (int64_t)(k * kmax + l) * ds;
+      if (g < G) {
+        int q = g;
+        for (; q + 3 * G < nq; q += 4 * G) {
+          int2 qe[4];
+          double d[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            qe[u] = s.qtab[q + u * G];
+            d[u] = dq[q + u * G];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+              const int sb = SLAB ? slab_base((pt[r].x >> 24) + (int)((unsigned)qe[u].x >> 24), L, S1) : 0;
+              w[r] += s.box[sb + pt[r].y + qe[u].y] * d[u];
+            }
+        }
+        for (; q < nq; q += G) {
+          const int2 qe = s.qtab[q];
+          const double d = dq[q];
+#pragma unroll
+          for (int r = 0; r < NPT; ++r) {
+            const int sb = SLAB ? slab_base((pt[r].x >> 24) + (int)((unsigned)qe.x >> 24), L, S1) : 0;
+            w[r] += s.box[sb + pt[r].y + qe.y] * d;
+          }
+        }
+      }
+    }
+    __syncthreads();  // the last matrix-vector product has read R
+#pragma unroll
+    for (int r = 0; r < NPT; ++r)
+      if (pv[r]) wb[g * gstride + pidx[r]] = w[r];
+    __syncthreads();
+    if (G > 1) {
+      if (g == 0 && pv[0]) {
+        double a = wb[pidx[0]];
+        for (int gg = 1; gg < G; ++gg) a += wb[gg * gstride + pidx[0]];
+        wb[pidx[0]] = a;
+      }
+      __syncthreads();
+    }
+    // J_ab += sum_p E_ab^p w_p, p in the (t, u, v) order of the Hermite table
+#pragma unroll
+    for (int r = 0; r < kJAb; ++r) {
+      if (!av[r]) continue;
+      double ez[kJV];
+#pragma unroll
+      for (int v = 0; v < kJV; ++v) ez[v] = v <= Lb ? s.brae[rz[r] + v] : 0.0;
+      double acc = 0.0;
+      int p = 0;
+      for (int t = 0; t <= Lb; ++t) {
+        const double et = s.brae[rx[r] + t];
+        for (int u = 0; u <= Lb - t; ++u) {
+          const double eu = et * s.brae[ry[r] + u];
+          const int nv = Lb - t - u + 1;
+          double sv = 0.0;
+#pragma unroll
+          for (int v = 0; v < kJV; ++v)
+            if (v < nv) sv += ez[v] * wb[p + v];
+          acc += eu * sv;
+          p += nv;
+        }
+      }
+      J[r] += acc;
+    }
+    __syncthreads();  // brae and wb are rewritten for the next bra pair
+  }
+#pragma unroll
+  for (int r = 0; r < kJAb; ++r)
+    if (av[r]) outJ[tid + r * kThreads] = J[r];
+}
+
+// Prologue and body for quartet q (shells from the quartet arrays, or PAIRS:
+// from the bra and ket lists) and its bra pairs ij0..ij1-1 (or all of them,
+// ij1 < 0); returns without writing when the contraction lengths are out of
+// range or ij0 is not a pair of the quartet.
+template <int LAY, int NPT, bool PAIRS>
+__device__ void jengine_quartet(const ClassParams& cp, unsigned char* lds, const double* __restrict__ boys_tab,
+                                const uint2* __restrict__ rtab_L, const double* __restrict__ centers,
+                                const double* __restrict__ exps, const double* __restrict__ coefs,
+                                const int32_t* __restrict__ nprim, int64_t q, const double* __restrict__ kcenters,
+                                const double* __restrict__ kexps, const double* __restrict__ kcoefs, int64_t nket,
+                                int i0, int j0, bool all, const double* __restrict__ dket, int64_t ds,
+                                double* __restrict__ outJ, int64_t jstride, int tid, int wave, int lane) {
+  constexpr bool SLAB = LAY == kLaySlab;
+  Lds s;
+  s.sh = (double*)(lds + cp.o_shell);
+  s.baseM = (double*)(lds + cp.o_base);
+  s.kpair = s.baseM + 32;
+  s.bpair = s.kpair + 16;
+  s.pqv = s.bpair + 16;
+  s.ptab = (int2*)(lds + cp.o_ptab);
+  s.qtab = (int2*)(lds + cp.o_qtab);
+  s.box = (double*)(lds + cp.o_union);
+  s.box1 = (double*)(lds + cp.o_box1);
+  s.brae = (double*)(lds + cp.o_brae);
+  double* wb = (double*)(lds + cp.o_jw);
+  int* shn = (int*)(s.sh + 12 + 8 * cp.kmax);
+  load_shells<PAIRS>(s.sh, shn, cp.kmax, centers, exps, coefs, nprim, q, kcenters, kexps, kcoefs, nket, tid);
+  build_htab(s.ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, SLAB, tid);
+  build_htab(s.qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, SLAB, tid);
+  uint2 rent[SLAB ? kRPerThread : kRPerBox];
+  load_rtab(rent, rtab_L, cp.L, tid);
+  __syncthreads();
+  const int kmax = cp.kmax;
+  const int Ka = shn[0], Kb = shn[1], Kc = shn[2], Kd = shn[3];
+  const bool ok = Ka >= 1 && Ka <= kmax && Kb >= 1 && Kb <= kmax && Kc >= 1 && Kc <= kmax && Kd >= 1 && Kd <= kmax;
+  if (!ok || (!all && (i0 >= Ka || j0 >= Kb))) {
+    __syncthreads();
+    return;
+  }
+  const int ij0 = all ? 0 : i0 * Kb + j0;
+  const int ij1 = all ? Ka * Kb : ij0 + 1;
+  jengine_body<LAY, NPT>(cp, s, wb, boys_tab, rent, Ka, Kb, Kc, Kd, ij0, ij1, dket, ds,
+                         outJ + (all ? 0 : (int64_t)ij0 * jstride), tid, wave, lane);
+}
+
+// Batch form: one workgroup per (quartet q0 + blockIdx.x / kmax^2, bra
+// primitive pair (i, j) = divmod(blockIdx.x % kmax^2, kmax)); its J^ij goes to
+// part + ((blockIdx.x / kmax^2) * kmax^2 + i * Kb + j) * nab.
+template <int LAY, int NPT>
 __global__ __launch_bounds__(kThreads, 1) void eri4_coulomb_kernel(
     const ClassParams cp, const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
     const double* __restrict__ centers, const double* __restrict__ exps, const double* __restrict__ coefs,
-    const int32_t* __restrict__ nprim, double* __restrict__ out, int64_t q0, const double* __restrict__ dket,
+    const int32_t* __restrict__ nprim, double* __restrict__ part, int64_t q0, const double* __restrict__ dket,
     int64_t ds) {
   extern __shared__ __align__(16) unsigned char lds[];
-  __shared__ double jt[kCoulLds];  // J rows of the tile and the waves' partial rows
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t i = blockIdx.x / cp.nrt;
-  const int64_t q = q0 + i;
-  const int rt = blockIdx.x % cp.nrt;
   const int64_t kk2 = (int64_t)cp.kmax * cp.kmax;
-  process_tile<RB, LAY, false, false, false, true>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
-                                                   out + q * (int64_t)cp.nab, q, rt, tid, wave, lane, nullptr,
-                                                   nullptr, nullptr, 0, nullptr, dket + i * kk2 * ds, 0, ds, jt);
+  const int64_t iq = blockIdx.x / kk2;
+  const int slot = (int)(blockIdx.x - iq * kk2);
+  const int i = slot / cp.kmax, j = slot - (slot / cp.kmax) * cp.kmax;
+  jengine_quartet<LAY, NPT, false>(cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim, q0 + iq,
+                                   nullptr, nullptr, nullptr, 0, i, j, false, dket + iq * kk2 * ds, ds,
+                                   part + iq * kk2 * cp.nab, cp.nab, tid, wave, lane);
 }
 
-template <int RB, int LAY>
+// J of quartet q0 + blockIdx.x: the sum over its bra primitive pairs s = 0 ..
+// Ka*Kb-1, in that order, of part[(blockIdx.x * kmax^2 + s) * nab ..]; NaN for
+// a quartet whose contraction lengths are out of range.
+__global__ void coulomb_pairsum_kernel(const ClassParams cp, const int32_t* __restrict__ nprim,
+                                       const double* __restrict__ part, double* __restrict__ out, int64_t q0) {
+  const int64_t iq = blockIdx.x, q = q0 + iq;
+  const int kmax = cp.kmax;
+  const int Ka = nprim[q * 4], Kb = nprim[q * 4 + 1], Kc = nprim[q * 4 + 2], Kd = nprim[q * 4 + 3];
+  const bool ok = Ka >= 1 && Ka <= kmax && Kb >= 1 && Kb <= kmax && Kc >= 1 && Kc <= kmax && Kd >= 1 && Kd <= kmax;
+  const int64_t kk2 = (int64_t)kmax * kmax;
+  const double* p = part + iq * kk2 * cp.nab;
+  for (int ab = threadIdx.x; ab < cp.nab; ab += blockDim.x) {
+    double a = ok ? 0.0 : __builtin_nan("");
+    if (ok)
+      for (int s = 0; s < Ka * Kb; ++s) a += p[(int64_t)s * cp.nab + ab];
+    out[q * cp.nab + ab] = a;
+  }
+}
+
+template <int LAY, int NPT>
 hipError_t coulomb_launch_t(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
-                            const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0,
+                            const double* exps, const double* coefs, const int32_t* nprim, double* part, int64_t q0,
                             const double* dket, int64_t ds) {
-  hipLaunchKernelGGL((eri4_coulomb_kernel<RB, LAY>), grid, dim3(kThreads), p.lds_bytes, s, p, t.boys, t.rtab, centers,
-                     exps, coefs, nprim, out, q0, dket, ds);
+  hipLaunchKernelGGL((eri4_coulomb_kernel<LAY, NPT>), grid, dim3(kThreads), p.lds_bytes, s, p, t.boys, t.rtab,
+                     centers, exps, coefs, nprim, part, q0, dket, ds);
   return hipGetLastError();
 }
 
-// Persistent kernel of a Coulomb pair-list plan: the work loop of
-// eri4_plan_kernel (shells from the lists), each tile contracting [ab|q] with
-// the dket of the quartet's ket entry (dket + dkoff[q % nket]) and writing its
-// J rows to jpart + qoff[q].
+// Persistent kernel of a Coulomb pair-list plan: work items are whole quartets
+// (largest first); each sums J over all its bra primitive pairs with the dket
+// of its ket entry (dket + dkoff[q % nket]) and writes it to jpart + qoff[q].
 __global__ __launch_bounds__(kThreads, 1) void eri4_plan_coulomb_kernel(
     const ClassParams* __restrict__ classes, const int2* __restrict__ items, int nitems,
     const int64_t* __restrict__ qoff, const int32_t* __restrict__ nprim, int* __restrict__ counter,
@@ -134,7 +366,6 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_plan_coulomb_kernel(
     const double* __restrict__ kcenters, const double* __restrict__ kexps, const double* __restrict__ kcoefs,
     int64_t nket, const int64_t* __restrict__ dkoff, const double* __restrict__ dket) {
   extern __shared__ __align__(16) unsigned char lds[];
-  __shared__ double jt[kCoulLds];
   __shared__ int next_item;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -148,22 +379,20 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_plan_coulomb_kernel(
     const int q = __builtin_amdgcn_readfirstlane(w.x);
     const int rc = __builtin_amdgcn_readfirstlane(w.y);
     const ClassParams cp = classes[rc >> 16];
-    const int rt = rc & 0xffff;
     const uint2* rt_L = rtab + cp.rtab_off;
-    double* oq = jpart + qoff[q];
     const int64_t ik = q - (q / nket) * nket;
-    const double* hk = dket + dkoff[ik];
-    const int64_t hks = 16 * (int64_t)cp.nqb;
-#define T(RB, LAY)                                                                                                   \
-  process_tile<RB, LAY, false, true, false, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, oq, q, rt, tid, \
-                                                  wave, lane, kcenters, kexps, kcoefs, nket, nullptr, hk, 0, hks, jt)
-    const int lay = cp.lay;
-    if (lay == kLaySlab) {
-      if (cp.rb == 2) T(2, kLaySlab); else T(1, kLaySlab);
-    } else if (lay == kLayBox2) {
-      if (cp.rb == 4) T(4, kLayBox2); else if (cp.rb == 2) T(2, kLayBox2); else T(1, kLayBox2);
+    const double* dk = dket + dkoff[ik];
+    const int64_t ds = 16 * (int64_t)cp.nqb;
+#define T(LAY, NPT)                                                                                                \
+  jengine_quartet<LAY, NPT, true>(cp, lds, boys_tab, rt_L, centers, exps, coefs, nprim, q, kcenters, kexps, kcoefs, \
+                                  nket, 0, 0, true, dk, ds, jpart + qoff[q], 0, tid, wave, lane)
+    const bool two = cp.np > kThreads;
+    if (cp.lay == kLaySlab) {
+      if (two) T(kLaySlab, 2); else T(kLaySlab, 1);
+    } else if (cp.lay == kLayBox2) {
+      if (two) T(kLayBox2, 2); else T(kLayBox2, 1);
     } else {
-      if (cp.rb == 4) T(4, kLayBox); else if (cp.rb == 2) T(2, kLayBox); else T(1, kLayBox);
+      if (two) T(kLayBox, 2); else T(kLayBox, 1);
     }
 #undef T
   }
@@ -188,7 +417,7 @@ __global__ void coulomb_reduce_kernel(int64_t nket, const int32_t* __restrict__ 
 
 hipError_t plan_coulomb_set_attrs() {
   return hipFuncSetAttribute((const void*)eri4_plan_coulomb_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             kMaxLdsBytes - kCoulLds * 8 - 512);
+                             kMaxLdsBytes - 64);
 }
 
 hipError_t plan_coulomb_occupancy(int lds_bytes, int* per_cu) {
@@ -218,13 +447,11 @@ hipError_t plan_coulomb_launch(dim3 grid, int lds_bytes, hipStream_t s, const Ta
 }
 
 hipError_t coulomb_set_attrs() {
-  const void* k[8] = {(const void*)eri4_coulomb_kernel<1, kLayBox>,  (const void*)eri4_coulomb_kernel<2, kLayBox>,
-                      (const void*)eri4_coulomb_kernel<4, kLayBox>,  (const void*)eri4_coulomb_kernel<1, kLaySlab>,
-                      (const void*)eri4_coulomb_kernel<2, kLaySlab>, (const void*)eri4_coulomb_kernel<1, kLayBox2>,
-                      (const void*)eri4_coulomb_kernel<2, kLayBox2>, (const void*)eri4_coulomb_kernel<4, kLayBox2>};
+  const void* k[6] = {(const void*)eri4_coulomb_kernel<kLayBox, 1>,  (const void*)eri4_coulomb_kernel<kLayBox, 2>,
+                      (const void*)eri4_coulomb_kernel<kLaySlab, 1>, (const void*)eri4_coulomb_kernel<kLaySlab, 2>,
+                      (const void*)eri4_coulomb_kernel<kLayBox2, 1>, (const void*)eri4_coulomb_kernel<kLayBox2, 2>};
   for (const void* f : k) {
-    const hipError_t e =
-        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes - kCoulLds * 8 - 512);
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -239,22 +466,29 @@ hipError_t coulomb_dket_launch(const ClassParams& p, int64_t nq, hipStream_t s, 
   return hipGetLastError();
 }
 
-hipError_t coulomb_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
-                          const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0,
-                          const double* dket, int64_t ds) {
-  const bool two = p.rb == 2;
-#define L(RB, LAY) coulomb_launch_t<RB, LAY>(p, grid, s, t, centers, exps, coefs, nprim, out, q0, dket, ds)
+// J of quartets q0..q0+nq-1: the J^ij of every bra primitive pair into part
+// (kmax^2 * nab doubles per quartet), then their sum per quartet into out.
+hipError_t coulomb_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
+                          const double* exps, const double* coefs, const int32_t* nprim, double* part, double* out,
+                          int64_t q0, const double* dket, int64_t ds) {
+  const dim3 grid((unsigned)(nq * p.kmax * p.kmax));
+  const bool two = p.np > kThreads;
+  hipError_t e;
+#define L(LAY, NPT) coulomb_launch_t<LAY, NPT>(p, grid, s, t, centers, exps, coefs, nprim, part, q0, dket, ds)
   switch (p.lay) {
     case kLaySlab:
-      return two ? L(2, kLaySlab) : L(1, kLaySlab);
+      e = two ? L(kLaySlab, 2) : L(kLaySlab, 1);
+      break;
     case kLayBox2:
-      if (p.rb == 4) return L(4, kLayBox2);
-      return two ? L(2, kLayBox2) : L(1, kLayBox2);
+      e = two ? L(kLayBox2, 2) : L(kLayBox2, 1);
+      break;
     default:
-      if (p.rb == 4) return L(4, kLayBox);
-      return two ? L(2, kLayBox) : L(1, kLayBox);
+      e = two ? L(kLayBox, 2) : L(kLayBox, 1);
   }
 #undef L
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(coulomb_pairsum_kernel, dim3((unsigned)nq), dim3(256), 0, s, p, nprim, part, out, q0);
+  return hipGetLastError();
 }
 
 }  // namespace eri4

@@ -660,6 +660,30 @@ struct Lds {
   int2 *ptab, *qtab;
 };
 
+// P - Q into s.pqv and [0]^(m) = (-2 rho)^m 2 pi^(5/2) / (zp zq sqrt(zp + zq))
+// w_bra w_ket F_m(rho |PQ|^2) for m = 0..L into s.baseM (eq. (md1)'s start,
+// with the pair weights of s.bpair[1], s.kpair[1] and the scale s.kpair[11]
+// folded in), for the pairs in s.bpair and s.kpair.  Called by one wave.
+__device__ __forceinline__ void hermite_base(const Lds& s, int L, const double* __restrict__ boys_tab, int lane) {
+  if (lane < 3) s.pqv[lane] = s.bpair[2 + lane] - s.kpair[2 + lane];
+  if (lane <= L) {
+    const double pref = 2.0 * pow(M_PI, 2.5);
+    const double zp = s.bpair[0], zq = s.kpair[0];
+    const double zs = zp + zq;
+    const double rho = zp * zq / zs;
+    double r2 = 0.0;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      const double d = s.bpair[2 + x] - s.kpair[2 + x];
+      r2 += d * d;
+    }
+    const double F = boys_fm(lane, rho * r2, boys_tab);
+    double pw = 1.0;
+    for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
+    s.baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (s.bpair[1] * (s.kpair[1] * s.kpair[11])) * F;
+  }
+}
+
 constexpr int kGroup = 4;  // output column blocks per second-transform pass
 
 // Power-of-two scale of [0]^(m) for the ket pair in s.kpair (FP32 transforms
@@ -698,30 +722,20 @@ __device__ __forceinline__ void ket_scale(const Lds& s, int kmax, int Ka, int Kb
 // their H matrices from hb / hk (this quartet's, hbs / hks doubles per
 // primitive pair, pair (i, j) of shells with K1, K2 primitives at slot
 // i * K2 + j); FP64 only.
-// COUL: no second transform; the first transform's [ab|q] is contracted with
-// the ket density in Hermite space, dket[q] = sum_cd E_cd^q D_cd of ket pair
-// (k, l) at hk + (k * kmax + l) * hks (coulomb_dket_kernel), giving
-// J_ab = sum_cd (ab|cd) D_cd, written to outq[ab] (FP64, Cartesian).
 // EXCH: no second transform either; bra rows are ordered (b, a) with a padded
 // to a multiple of 16 (exch_row), so each 16-row block has one b, and [ab|q]
 // is contracted on the matrix cores with F^b[q][c] = sum_d E_cd^q D_bd of ket
 // pair (k, l) (exchange_f_kernel, at hk + (k * kmax + l) * hks in operand
 // order), accumulated over the ket pairs into y[a][c] = sum_d (ab|cd) D_bd,
 // written to outq[(b * na + a) * nc + c] for the tile's b (FP64, Cartesian).
-template <int NR, int NC1, int LAY, bool F32, bool SOLID = false, bool COUL = false, bool EXCH = false>
+template <int NR, int NC1, int LAY, bool F32, bool SOLID = false, bool EXCH = false>
 __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, const double* __restrict__ boys_tab,
                            const uint2 (&rent)[LAY == kLaySlab ? kRPerThread : kRPerBox], double* __restrict__ outq,
                            int row0, int Ka, int Kb, int Kc, int Kd, int tid, int wave, int lane,
                            const double* __restrict__ hb = nullptr, const double* __restrict__ hk = nullptr,
-                           int64_t hbs = 0, int64_t hks = 0, double* jt = nullptr) {
+                           int64_t hbs = 0, int64_t hks = 0) {
   static_assert(!(SOLID && F32), "solid-harmonic output runs FP64 transforms");
-  static_assert(!(COUL && (F32 || SOLID)), "the Coulomb contraction runs FP64 Cartesian transforms");
-  static_assert(!(EXCH && (F32 || SOLID || COUL)), "the exchange contraction runs FP64 Cartesian transforms");
-  if constexpr (COUL) {
-    // J rows of the tile in jt[0..63], each wave's partial rows in
-    // jt[64 + 64 * wave ..] (kCoulLds doubles of the kernel's LDS)
-    if (tid < 64) jt[tid] = 0.0;
-  }
+  static_assert(!(EXCH && (F32 || SOLID)), "the exchange contraction runs FP64 Cartesian transforms");
   constexpr bool SLAB = LAY == kLaySlab;
   const int kmax = cp.kmax;
   const double* A = s.sh;
@@ -771,7 +785,6 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
   }
   const int ncbw = (wave < cp.ncdb) ? (cp.ncdb - wave + 7) / 8 : 0;  // output column blocks of this wave
 
-  const double pref = 2.0 * pow(M_PI, 2.5);
   StageClock clk;
   clk.start();
   // EXCH: y blocks (row block, 16 columns c) of this wave, kept over the ket pairs
@@ -797,22 +810,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       __syncthreads();
       ERI4_STAGE(kStPair);
       if (wave == 0) {
-        if (lane < 3) s.pqv[lane] = s.bpair[2 + lane] - s.kpair[2 + lane];
-        if (lane <= cp.L) {
-          const double zp = s.bpair[0], zq = s.kpair[0];
-          const double zs = zp + zq;
-          const double rho = zp * zq / zs;
-          double r2 = 0.0;
-#pragma unroll
-          for (int x = 0; x < 3; ++x) {
-            const double d = s.bpair[2 + x] - s.kpair[2 + x];
-            r2 += d * d;
-          }
-          const double F = boys_fm(lane, rho * r2, boys_tab);
-          double pw = 1.0;
-          for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
-          s.baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (s.bpair[1] * (s.kpair[1] * s.kpair[11])) * F;
-        }
+        hermite_base(s, cp.L, boys_tab, lane);
       } else if constexpr (!SOLID) {
         if (wave == 1)
           build_etab(s.brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / s.bpair[0], s.bpair + 5, s.bpair + 8, false,
@@ -837,44 +835,6 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
       ERI4_STAGE(kStGemm1);
     }
 
-    if constexpr (COUL) {
-      // J rows += sum over this wave's columns q of [ab|q] dket[q]; the 16
-      // lanes of a row group hold 16 columns: reduce them, then add the waves'
-      // partial rows in a fixed order (reproducible to the bit)
-      const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
-      const double* dk = hk + (k * kmax + l) * hks;
-      double part[NR][4];
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) part[r][jj] = 0.0;
-#pragma unroll
-      for (int c = 0; c < NC1; ++c) {
-        const double dv = dk[(wave + 8 * c) * 16 + (lane & 15)];
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) part[r][jj] += acc1[r][c][jj] * dv;
-      }
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          double v = part[r][jj];
-#pragma unroll
-          for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
-          if ((lane & 15) == 0) jt[64 + 64 * wave + r * 16 + acc_row<false>(jj, lane >> 4)] = v;
-        }
-      __syncthreads();
-      if (tid < NR * 16) {
-        double a = jt[tid];
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) a += jt[64 + 64 * w + tid];
-        jt[tid] = a;
-      }
-      __syncthreads();
-      continue;
-    }
     // [ab_tile|q] -> LDS (aliases the R box); ket tables for kl
     if constexpr (NC1 > 0) {
 #pragma unroll
@@ -940,11 +900,45 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
     ERI4_STAGE(kStGemm2);
   }
   clk.flush(tid);
-  if constexpr (COUL) {
-    __syncthreads();
-    if (tid < NR * 16 && row0 + tid < cp.nab) outq[row0 + tid] = jt[tid];
-  }
   if constexpr (EXCH) exch_store<NR>(cp, yacc, outq, row0, wave, lane);
+}
+
+// Shell data of quartet q into LDS: centres A B C D in sh[0..11], then the
+// exponents and the coefficients of shells a b c d (kmax each), and the four
+// contraction lengths in shn[0..3].  PAIRS: the bra pair is entry q / nket of
+// the bra list (centers, exps, coefs as [n][2][...]) and the ket pair entry
+// q % nket of the ket list.  Called by all threads; the caller synchronises.
+template <bool PAIRS>
+__device__ __forceinline__ void load_shells(double* sh, int* shn, int kmax, const double* __restrict__ centers,
+                                            const double* __restrict__ exps, const double* __restrict__ coefs,
+                                            const int32_t* __restrict__ nprim, int64_t q,
+                                            const double* __restrict__ kcenters, const double* __restrict__ kexps,
+                                            const double* __restrict__ kcoefs, int64_t nket, int tid) {
+  if constexpr (!PAIRS) {
+    if (tid < 12) {
+      sh[tid] = centers[q * 12 + tid];
+    } else if (tid < 12 + 8 * kmax) {
+      const int j = tid - 12;
+      sh[tid] = (j < 4 * kmax) ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)];
+    } else if (tid >= 256 && tid < 260) {
+      shn[tid - 256] = nprim[q * 4 + (tid - 256)];
+    }
+  } else {
+    const int64_t ib = q / nket, ik = q - ib * nket;
+    if (tid < 12) {
+      sh[tid] = tid < 6 ? centers[ib * 6 + tid] : kcenters[ik * 6 + (tid - 6)];
+    } else if (tid < 12 + 8 * kmax) {
+      const int j = tid - 12;
+      const bool ex = j < 4 * kmax;
+      const int jj = ex ? j : j - 4 * kmax;  // shell jj / kmax, primitive jj % kmax
+      if (jj < 2 * kmax)
+        sh[tid] = (ex ? exps : coefs)[ib * 2 * kmax + jj];
+      else
+        sh[tid] = (ex ? kexps : kcoefs)[ik * 2 * kmax + (jj - 2 * kmax)];
+    } else if (tid >= 256 && tid < 260) {
+      shn[tid - 256] = nprim[q * 4 + (tid - 256)];
+    }
+  }
 }
 
 // All the work of one tile: quartet q, bra rows rt*RB*16.., whose integrals
@@ -954,7 +948,7 @@ __device__ __forceinline__ void fused_body(const ClassParams& cp, const Lds& s, 
 // pairs (PAIRS true: bra pair q / nket, ket pair q % nket, each list centers
 // [i][2][3], exps/coefs [i][2][kmax]; centers/exps/coefs are the bra list).
 // SOLID: solid-harmonic rows and columns, H matrices from hb / hk (fused_body).
-template <int RB, int LAY, bool F32, bool PAIRS, bool SOLID = false, bool COUL = false, bool EXCH = false>
+template <int RB, int LAY, bool F32, bool PAIRS, bool SOLID = false, bool EXCH = false>
 __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned char* lds,
                                              const double* __restrict__ boys_tab,
                                              const uint2* __restrict__ rtab_L,
@@ -965,7 +959,7 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
                                              const double* __restrict__ kexps, const double* __restrict__ kcoefs,
                                              int64_t nket, const double* __restrict__ hb = nullptr,
                                              const double* __restrict__ hk = nullptr, int64_t hbs = 0,
-                                             int64_t hks = 0, double* jt = nullptr) {
+                                             int64_t hks = 0) {
   constexpr bool SLAB = LAY == kLaySlab;
   const int kmax = cp.kmax;
   Lds s;
@@ -982,34 +976,7 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
   s.X = (double*)(lds + cp.o_union);
   s.kete = (double*)(lds + cp.o_kete);
   int* shn = (int*)(s.sh + 12 + 8 * kmax);
-
-  // shell data of this quartet: centres A B C D, then exponents and
-  // coefficients of shells a b c d (kmax each)
-  if constexpr (!PAIRS) {
-    if (tid < 12) {
-      s.sh[tid] = centers[q * 12 + tid];
-    } else if (tid < 12 + 8 * kmax) {
-      const int j = tid - 12;
-      s.sh[tid] = (j < 4 * kmax) ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)];
-    } else if (tid >= 256 && tid < 260) {
-      shn[tid - 256] = nprim[q * 4 + (tid - 256)];
-    }
-  } else {
-    const int64_t ib = q / nket, ik = q - ib * nket;
-    if (tid < 12) {
-      s.sh[tid] = tid < 6 ? centers[ib * 6 + tid] : kcenters[ik * 6 + (tid - 6)];
-    } else if (tid < 12 + 8 * kmax) {
-      const int j = tid - 12;
-      const bool ex = j < 4 * kmax;
-      const int jj = ex ? j : j - 4 * kmax;  // shell jj / kmax, primitive jj % kmax
-      if (jj < 2 * kmax)
-        s.sh[tid] = (ex ? exps : coefs)[ib * 2 * kmax + jj];
-      else
-        s.sh[tid] = (ex ? kexps : kcoefs)[ik * 2 * kmax + (jj - 2 * kmax)];
-    } else if (tid >= 256 && tid < 260) {
-      shn[tid - 256] = nprim[q * 4 + (tid - 256)];
-    }
-  }
+  load_shells<PAIRS>(s.sh, shn, kmax, centers, exps, coefs, nprim, q, kcenters, kexps, kcoefs, nket, tid);
   build_htab(s.ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, SLAB, tid);
   build_htab(s.qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, SLAB, tid);
   uint2 rent[SLAB ? kRPerThread : kRPerBox];
@@ -1028,7 +995,7 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
       }
     } else {
       const int nrows = min(RB * 16, cp.nab - row0);
-      const int ncols = COUL ? 1 : cp.ncd;
+      const int ncols = cp.ncd;
       double* o = outq + (int64_t)row0 * ncols;
       for (int i = tid; i < nrows * ncols; i += kThreads) o[i] = __builtin_nan("");
     }
@@ -1039,8 +1006,8 @@ __device__ __forceinline__ void process_tile(const ClassParams& cp, unsigned cha
   const int nrows_all = EXCH ? cp.nb * 16 * ((cp.na + 15) / 16) : cp.nab;           // (padded) bra rows
   const int nrv = min(RB, (nrows_all - row0 + 15) / 16);                          // valid row blocks of this tile
 #define BODY(NR, NC1) \
-  fused_body<NR, NC1, LAY, F32, SOLID, COUL, EXCH>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane, \
-                                                   hb, hk, hbs, hks, jt)
+  fused_body<NR, NC1, LAY, F32, SOLID, EXCH>(cp, s, boys_tab, rent, outq, row0, Ka, Kb, Kc, Kd, tid, wave, lane, hb, \
+                                             hk, hbs, hks)
   constexpr int NR2 = RB >= 2 ? 2 : 1;
   if constexpr (RB == 4) {
     // 64-row tiles (kets with at most 2 column blocks per wave): the last tile

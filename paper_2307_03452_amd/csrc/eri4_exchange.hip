@@ -112,10 +112,10 @@ __global__ __launch_bounds__(kThreads, 1) void eri4_exchange_kernel(
   const int64_t q = q0 + i;
   const int rt = blockIdx.x % cp.nrt;
   const int64_t kk2 = (int64_t)cp.kmax * cp.kmax;
-  process_tile<RB, LAY, false, false, false, false, true>(
+  process_tile<RB, LAY, false, false, false, true>(
       cp, lds, boys_tab, rtab + cp.rtab_off, centers, exps, coefs, nprim,
       part + i * (int64_t)cp.nb * cp.na * cp.nc, q, rt, tid, wave, lane, nullptr, nullptr, nullptr, 0, nullptr,
-      fb + i * kk2 * fss, 0, fss, nullptr);
+      fb + i * kk2 * fss, 0, fss);
 }
 
 // K[q0 + blockIdx.x][a][c] = sum over b = 0..nb-1, in that order, of the

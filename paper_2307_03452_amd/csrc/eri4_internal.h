@@ -79,9 +79,10 @@ __host__ __device__ constexpr int solid_pair_units(int l1, int l2, bool ket) {
   return ket ? ((2 * l1 + 1) * (2 * l2 + 1) + 15) / 16 : 4 * (((2 * l1 + 1) * (2 * l2 + 1) + 63) / 64);
 }
 
-// Static LDS of the Coulomb kernels: J rows of a tile plus one partial row set
-// per wave (doubles).
-constexpr int kCoulLds = 64 + 8 * 64;
+// Doubles of the Coulomb kernels' w buffer: the bra Hermite functions of up to
+// 8 groups of waves (at most 512 in all), or 2 per thread when there are more
+// than 512 (la + lb >= 13).
+constexpr int kJw = 1024;
 
 // LDS of one compute unit (gfx950).
 constexpr int kMaxLdsBytes = 160 * 1024;
@@ -133,6 +134,7 @@ struct ClassParams {
   int o_brae;    // bra tables (phase 1)
   int o_kete;    // ket tables (phase 2)
   int o_ptab, o_qtab, o_base, o_shell;
+  int o_jw;      // Coulomb (J-engine) kernels: the Hermite-space J vector w
   int lds_bytes;
 };
 

@@ -42,14 +42,16 @@ hipError_t solid_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Ta
 
 // Coulomb contraction (eri4_coulomb.hip): dket of every ket primitive pair of
 // quartets q0..q0+nq-1 (ds doubles each, kmax^2 slots per quartet), then the
-// integral kernels that contract [ab|q] with it.
+// J-engine kernel (J^ij of every bra primitive pair into part, kmax^2 * nab
+// doubles per quartet) and the sum over bra pairs into out.  p from
+// jengine_params.
 hipError_t coulomb_set_attrs();
 hipError_t coulomb_dket_launch(const ClassParams& p, int64_t nq, hipStream_t s, const double* centers,
                                const double* exps, const double* coefs, const int32_t* nprim, const double* dens,
                                double* dket, int64_t q0, int64_t ds);
-hipError_t coulomb_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Tables& t, const double* centers,
-                          const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0,
-                          const double* dket, int64_t ds);
+hipError_t coulomb_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
+                          const double* exps, const double* coefs, const int32_t* nprim, double* part, double* out,
+                          int64_t q0, const double* dket, int64_t ds);
 
 // Exchange contraction (eri4_exchange.hip): F^b of every ket primitive pair
 // and shell-b component of quartets q0..q0+nq-1 (fbs doubles each), the

@@ -242,7 +242,9 @@ def test_solid_work_size_and_host_errors():
 def test_coulomb_work_size_and_host_errors():
     L = eri4.lib()
     n1 = eri4.coulomb_work_size((6, 6, 6, 6), 1, 1)
-    assert n1 == 16 * 29  # 455 ket Hermite functions in 29 column blocks of 16
+    # per primitive pair slot: dket (455 ket Hermite functions in 29 blocks of
+    # 16) and one bra pair's J rows (28 x 28)
+    assert n1 == 16 * 29 + 28 * 28
     assert eri4.coulomb_work_size((6, 6, 6, 6), 3, 2) == 2 * 9 * n1
     assert L.eri4_coulomb_work_size(0, 0, 0, 8, 1, 1) == -1
     p = ctypes.c_void_p(16)  # never dereferenced: the calls fail on the host first
