@@ -11,22 +11,23 @@ namespace {
 // H = (C_1 x C_2) E for one primitive pair (Sec. 2, the contraction of E with
 // the Cartesian-to-solid coefficients), written in the operand order of the
 // transform that reads it (see gemm1_h): one workgroup per (quartet q0 +
-// blockIdx.x, side = blockIdx.y & 1, pair slot blockIdx.y >> 1 = i * kmax + j).
-// Side 0 is the bra (shells a, b; units of 16 rows, cp.nrt * cp.rb of them,
-// cp.np4 k), side 1 the ket (shells c, d, sign (-1)^|q| of eq. (pq); cp.ncdb
-// units of 16 columns, cp.nq4 k).  Elements past the solid functions or the
-// Hermite functions are 0.  Pairs beyond the quartet's contraction lengths are
-// skipped (the integral kernel does not read them).
+// blockIdx.x, side = blockIdx.y & 1, pair slot).  Side 0 is the bra (shells a,
+// b; cp.nrt * cp.rb units of 16 rows, cp.np4 k), side 1 the ket (shells c, d,
+// sign (-1)^|q| of eq. (pq); cp.ncdb units of 16 columns, cp.nq4 k).  Elements
+// past the solid functions or the Hermite functions are 0.  Pairs beyond the
+// quartet's contraction lengths are skipped (the integral kernel does not read
+// them).
 //
-// The sum is taken in two steps per chunk of kHChunk Hermite indices k and
-// per solid function m1 of the first shell:
-//   P[b][k]     = sum_a C_1[m1][a] E_ab^k      (b over Cartesians of shell 2)
-//   H[m1 m2][k] = sum_b C_2[m2][b] P[b][k]
-// with the lanes of a wave on consecutive k (the same coefficient lists); H is
-// stored straight into operand order.  Rows past the solid functions are
-// zero-filled first.
-constexpr int kHChunk = 64;
-constexpr int kSolidHLds = ncart(kTableLMax) * kHChunk * 8;
+// Both sums run on the FP64 matrix cores, per chunk of 16 Hermite indices k:
+//   P[m1][b][k]  = sum_a C_1[m1][a] E_ab^k   (16 x 4 steps over a, one 16-wide
+//                                             block of k per shell-2 component b)
+//   H[m1 m2][k] = sum_b C_2[m2][b] P[m1][b][k]
+// with the coefficients as the A operands (dense, from the sparse table, in
+// registers) and E_ab^k formed once per (a, b, k) from the three 1-d tables as
+// the B operand of the first product; P goes through LDS.
+constexpr int kHNc = ncart(kTableLMax);                // Cartesian components per shell, at most
+constexpr int kHSteps = (kHNc + 3) / 4;                // MFMA k steps over them
+constexpr int kSolidHLds = 16 * kHNc * 16 * 8;         // P of one chunk: [16 m1][kHNc b][16 k]
 
 // H of primitives (z1, w1) of shell l1 and (z2, w2) of shell l2 at centres
 // c[0..2], c[3..5], into H (this pair slot's nunits units of 16 rows by nk4 k).
@@ -37,37 +38,35 @@ __device__ __forceinline__ void build_h(int l1, int l2, bool ket, const double* 
   __shared__ double tabs[kMaxEtab];
   __shared__ double pair[16];
   __shared__ int2 htab[kMaxHerm];
-  __shared__ int4 terms[2][kSolidRows][kSolidTerms];  // (a_x, a_y, a_z, Cartesian index) per term
-  __shared__ double tcoef[2][kSolidRows][kSolidTerms];
-  __shared__ int tcount[2][kSolidRows];
-  const int lane = tid & 63;
+  __shared__ double cd[2][16][kHNc];  // dense C_1, C_2 (rows m, columns Cartesian index), zero-padded
+  __shared__ int cart[2][kHNc];       // table-row offsets (x, y, z packed) of each Cartesian component
+  const int lane = tid & 63, g = lane >> 4, n = lane & 15;
+  const int wave = tid >> 6;
   const int Lh = l1 + l2;
   const int nh = nherm(Lh);
   const int trow = odd_row(Lh + 2), taxis = ((l1 + 1) * (l2 + 1) + 1) * trow;
-  const int s1 = 2 * l1 + 1, s2 = 2 * l2 + 1, n2c = ncart(l2);
+  const int s1 = 2 * l1 + 1, s2 = 2 * l2 + 1, n1c = ncart(l1), n2c = ncart(l2);
   if (tid == 0) make_pair(pair, z1, z2, w1, w2, c, c + 3);
   build_htab(htab, Lh, nh, nk4, 0, 0, false, tid);
-  // the two shells' solid functions as lists of (exponents, Cartesian index, coefficient)
+  for (int e = tid; e < 2 * 16 * kHNc; e += kThreads) (&cd[0][0][0])[e] = 0.0;
+  for (int e = tid; e < 2 * kHNc; e += kThreads) {
+    const int sh = e / kHNc, k = e - sh * kHNc, l = sh ? l2 : l1;
+    int x = 0, y = 0, z = 0;
+    if (k < ncart(l)) cart_of(l, k, x, y, z);
+    cart[sh][k] = x | (y << 8) | (z << 16);
+  }
+  __syncthreads();
+  // the two shells' solid functions, scattered into dense rows
   for (int e = tid; e < 2 * kSolidRows * kSolidTerms; e += kThreads) {
     const int sh = e / (kSolidRows * kSolidTerms), rem = e - sh * (kSolidRows * kSolidTerms);
     const int m = rem / kSolidTerms, jt = rem - m * kSolidTerms;
     const int l = sh ? l2 : l1;
     if (m < 2 * l + 1) {
       const double* ent = stab + (l * kSolidRows + m) * kSolidEntry;
-      const int n = (int)ent[0];
-      if (jt == 0) tcount[sh][m] = n;
-      if (jt < n) {
-        const int k = (int)ent[1 + 2 * jt];
-        int x, y, z;
-        cart_of(l, k, x, y, z);
-        terms[sh][m][jt] = make_int4(x, y, z, k);
-        tcoef[sh][m][jt] = ent[2 + 2 * jt];
-      }
+      if (jt < (int)ent[0]) cd[sh][m][(int)ent[1 + 2 * jt]] = ent[2 + 2 * jt];
     }
   }
-  __syncthreads();
-  if (tid < 64)
-    build_etab(tabs, l1, l2, trow, taxis, 0.5 / pair[0], pair + 5, pair + 8, ket, lane);
+  if (tid < 64) build_etab(tabs, l1, l2, trow, taxis, 0.5 / pair[0], pair + 5, pair + 8, ket, lane);
   __syncthreads();
   const int per = nk4 * 16;  // doubles per unit of 16 rows
   // element (row r, k) of H in operand order
@@ -77,37 +76,54 @@ __device__ __forceinline__ void build_h(int l1, int l2, bool ket, const double* 
     const int r = nrow + e / nk4, k = e - (e / nk4) * nk4;
     H[at(r, k)] = 0.0;
   }
-  for (int c0 = 0; c0 < nk4; c0 += kHChunk) {
-    for (int m1 = 0; m1 < s1; ++m1) {
-      const int n1 = tcount[0][m1];
-      for (int e = tid; e < n2c * kHChunk; e += kThreads) {
-        const int b = e / kHChunk, kc = e - b * kHChunk, k = c0 + kc;
-        double v = 0.0;
-        if (k < nh) {
-          int bx, by, bz;
-          cart_of(l2, b, bx, by, bz);
-          const int hx = htab[k].x;
-          const int t = hx & 0xff, u = (hx >> 8) & 0xff, w = (hx >> 16) & 0xff;
-#pragma unroll 4
-          for (int a = 0; a < n1; ++a) {
-            const int4 ta = terms[0][m1][a];
-            v += tcoef[0][m1][a] * tabs[(ta.x * (l2 + 1) + bx) * trow + t] *
-                 tabs[taxis + (ta.y * (l2 + 1) + by) * trow + u] * tabs[2 * taxis + (ta.z * (l2 + 1) + bz) * trow + w];
-          }
+  // A operands: lane (n, g) holds C[n][4 s + g] for the k steps s
+  const int ks1 = (n1c + 3) >> 2, ks2 = (n2c + 3) >> 2;
+  double a1[kHSteps], a2[kHSteps];
+  int ra[kHSteps];  // 1-d table rows of shell-1 component 4 s + g (the last one past n1c)
+#pragma unroll
+  for (int st = 0; st < kHSteps; ++st) {
+    a1[st] = cd[0][n][4 * st + g];
+    a2[st] = cd[1][n][4 * st + g];
+    ra[st] = cart[0][min(4 * st + g, n1c - 1)];
+  }
+  for (int c0 = 0; c0 < nk4; c0 += 16) {
+    // this lane's Hermite index k = c0 + n (past nk4: the zero entry Lh + 1)
+    const int kk = c0 + n;
+    const int hx = kk < nk4 ? htab[kk].x : Lh + 1;
+    const int t = hx & 0xff, u = (hx >> 8) & 0xff, w = (hx >> 16) & 0xff;
+    // P[m1][b][k] = sum_a C_1[m1][a] E_ab^k, one 16 x 16 block per b
+    for (int b = wave; b < n2c; b += kWaves) {
+      const int cb = cart[1][b];
+      const int bx = cb & 0xff, by = (cb >> 8) & 0xff, bz = (cb >> 16) & 0xff;
+      d4 acc = acc_zero<false>();
+#pragma unroll
+      for (int st = 0; st < kHSteps; ++st) {
+        if (st < ks1) {
+          const int axp = ra[st];
+          const int ax = axp & 0xff, ay = (axp >> 8) & 0xff, az = (axp >> 16) & 0xff;
+          const double e = tabs[(ax * (l2 + 1) + bx) * trow + t] * tabs[taxis + (ay * (l2 + 1) + by) * trow + u] *
+                           tabs[2 * taxis + (az * (l2 + 1) + bz) * trow + w];
+          acc = mfma16<false>(a1[st], e, acc);
         }
-        P[e] = v;
       }
-      __syncthreads();
-      for (int e = tid; e < s2 * kHChunk; e += kThreads) {
-        const int m2 = e / kHChunk, kc = e - m2 * kHChunk, k = c0 + kc;
-        const int n2 = tcount[1][m2];
-        double v = 0.0;
-#pragma unroll 4
-        for (int b = 0; b < n2; ++b) v += tcoef[1][m2][b] * P[terms[1][m2][b].w * kHChunk + kc];
-        if (k < nk4) H[at(m1 * s2 + m2, k)] = v;
-      }
-      __syncthreads();
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) P[(acc_row<false>(jj, g) * kHNc + b) * 16 + n] = acc[jj];
     }
+    __syncthreads();
+    // H[m1 s2 + m2][k] = sum_b C_2[m2][b] P[m1][b][k]
+    for (int m1 = wave; m1 < s1; m1 += kWaves) {
+      d4 acc = acc_zero<false>();
+#pragma unroll
+      for (int st = 0; st < kHSteps; ++st) {
+        if (st < ks2) acc = mfma16<false>(a2[st], P[(m1 * kHNc + min(4 * st + g, n2c - 1)) * 16 + n], acc);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int m2 = acc_row<false>(jj, g);
+        if (m2 < s2 && kk < nk4) H[at(m1 * s2 + m2, kk)] = acc[jj];
+      }
+    }
+    __syncthreads();
   }
 }
 
