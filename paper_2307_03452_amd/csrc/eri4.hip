@@ -674,6 +674,7 @@ struct eri4_plan_s {
   bool solid = false;  // solid-harmonic output
   int64_t work = 0;    // doubles of caller workspace for the H matrices
   int64_t nentries = 0;      // solid plans: list entries whose H is built (2 per quartet for quartet plans)
+  int hlds = 0;              // solid plans: dynamic LDS of the H builder (its largest entry)
   int32_t* d_pl = nullptr;   // per list entry: l of its two shells (bra entries first)
   int32_t* d_pn = nullptr;   // per list entry: contraction lengths
   int64_t* d_hoff = nullptr; // per list entry: where its H matrices start in the workspace
@@ -1010,7 +1011,7 @@ static eri4_status plan_launch(eri4_plan plan, const Shells& shl, double* work, 
   eri4_status st = ensure_device(&d);
   if (st != ERI4_SUCCESS) return st;
   if (plan->solid)
-    HIP_TRY(solid_hpairs_launch(plan->pairs ? plan->nbra : -1, plan->nentries, plan->kmax, stream, plan->d_pl,
+    HIP_TRY(solid_hpairs_launch(plan->pairs ? plan->nbra : -1, plan->nentries, plan->kmax, plan->hlds, stream, plan->d_pl,
                                 plan->d_pn, shl, plan->d_hoff, d->stab, work));
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, plan->d_counter);
   HIP_TRY(hipGetLastError());
@@ -1051,8 +1052,10 @@ static eri4_status solid_entries(eri4_plan* plan, int64_t ne, int64_t nbra, cons
   for (int64_t e = 0; e < ne; ++e) {
     hoff[e] = off;
     const int l1 = pl[2 * e], l2 = pl[2 * e + 1];
+    const int nk4 = (nherm(l1 + l2) + 3) & ~3;
     off += (int64_t)pn[2 * e] * pn[2 * e + 1] * solid_pair_units(l1, l2, nbra < 0 ? (e & 1) != 0 : e >= nbra) * 16 *
-           ((nherm(l1 + l2) + 3) & ~3);
+           nk4;
+    p->hlds = std::max(p->hlds, solid_h_lds(l1, l2, nk4));
   }
   p->work = off;
   p->nentries = ne;

@@ -79,6 +79,13 @@ __host__ __device__ constexpr int solid_pair_units(int l1, int l2, bool ket) {
   return ket ? ((2 * l1 + 1) * (2 * l2 + 1) + 15) / 16 : 4 * (((2 * l1 + 1) * (2 * l2 + 1) + 63) / 64);
 }
 
+// Dynamic LDS (bytes) of the H-matrix builder for shells l1, l2 with nk4
+// Hermite indices: one chunk of P[2 l1 + 1][ncart(l2)][16], the three 1-d E
+// tables, the Hermite index table.
+__host__ __device__ constexpr int solid_h_lds(int l1, int l2, int nk4) {
+  return (2 * l1 + 1) * ncart(l2) * 16 * 8 + 3 * ((l1 + 1) * (l2 + 1) + 1) * odd_row(l1 + l2 + 2) * 8 + nk4 * 8;
+}
+
 // Doubles of the Coulomb kernels' w buffer: the bra Hermite functions of up to
 // 8 groups of waves (at most 512 in all), or 2 per thread when there are more
 // than 512 (la + lb >= 13).

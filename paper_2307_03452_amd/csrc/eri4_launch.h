@@ -102,8 +102,9 @@ hipError_t plan_coulomb_launch(dim3 grid, int lds_bytes, hipStream_t s, const Ta
                                int nbra, int kmax, const int32_t* pl, const int32_t* pn, const double* ket_dens,
                                const int64_t* doff, const int64_t* dkoff, const int64_t* joff, double* dket,
                                double* jpart, double* out);
-// nbra < 0: the alternating (quartet) form, all entries read from x.centers, ...
-hipError_t solid_hpairs_launch(int64_t nbra, int64_t nentries, int kmax, hipStream_t s, const int32_t* pl,
+// nbra < 0: the alternating (quartet) form, all entries read from x.centers, ...;
+// lds: dynamic LDS bytes, solid_h_lds of the largest entry
+hipError_t solid_hpairs_launch(int64_t nbra, int64_t nentries, int kmax, int lds, hipStream_t s, const int32_t* pl,
                                const int32_t* pn, const Shells& x, const int64_t* hoff, const double* stab,
                                double* h);
 

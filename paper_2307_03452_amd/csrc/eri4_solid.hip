@@ -25,19 +25,18 @@ namespace {
 // with the coefficients as the A operands (dense, from the sparse table, in
 // registers) and E_ab^k formed once per (a, b, k) from the three 1-d tables as
 // the B operand of the first product; P goes through LDS.
-constexpr int kHNc = ncart(kTableLMax);                // Cartesian components per shell, at most
-constexpr int kHSteps = (kHNc + 3) / 4;                // MFMA k steps over them
-constexpr int kSolidHLds = 16 * kHNc * 16 * 8;         // P of one chunk: [16 m1][kHNc b][16 k]
+constexpr int kHNc = ncart(kTableLMax);  // Cartesian components per shell, at most
+constexpr int kHSteps = (kHNc + 3) / 4;  // MFMA k steps over them
+constexpr int kSolidHLdsMax = solid_h_lds(kTableLMax, kTableLMax, kMaxHerm);
 
 // H of primitives (z1, w1) of shell l1 and (z2, w2) of shell l2 at centres
 // c[0..2], c[3..5], into H (this pair slot's nunits units of 16 rows by nk4 k).
-// Called by all threads of a workgroup; P is LDS for kSolidHLds bytes.
+// Called by all threads of a workgroup; dyn is LDS for solid_h_lds(l1, l2,
+// nk4) bytes: P, then the 1-d tables, then the Hermite index table.
 __device__ __forceinline__ void build_h(int l1, int l2, bool ket, const double* __restrict__ c, double z1, double z2,
                                         double w1, double w2, const double* __restrict__ stab, double* __restrict__ H,
-                                        int nunits, int nk4, double* P, int tid) {
-  __shared__ double tabs[kMaxEtab];
+                                        int nunits, int nk4, unsigned char* dyn, int tid) {
   __shared__ double pair[16];
-  __shared__ int2 htab[kMaxHerm];
   __shared__ double cd[2][16][kHNc];  // dense C_1, C_2 (rows m, columns Cartesian index), zero-padded
   __shared__ int cart[2][kHNc];       // table-row offsets (x, y, z packed) of each Cartesian component
   const int lane = tid & 63, g = lane >> 4, n = lane & 15;
@@ -46,6 +45,9 @@ __device__ __forceinline__ void build_h(int l1, int l2, bool ket, const double* 
   const int nh = nherm(Lh);
   const int trow = odd_row(Lh + 2), taxis = ((l1 + 1) * (l2 + 1) + 1) * trow;
   const int s1 = 2 * l1 + 1, s2 = 2 * l2 + 1, n1c = ncart(l1), n2c = ncart(l2);
+  double* P = (double*)dyn;        // [s1][n2c][16]
+  double* tabs = P + s1 * n2c * 16;  // 3 * taxis
+  int2* htab = (int2*)(tabs + 3 * taxis);
   if (tid == 0) make_pair(pair, z1, z2, w1, w2, c, c + 3);
   build_htab(htab, Lh, nh, nk4, 0, 0, false, tid);
   for (int e = tid; e < 2 * 16 * kHNc; e += kThreads) (&cd[0][0][0])[e] = 0.0;
@@ -107,7 +109,10 @@ __device__ __forceinline__ void build_h(int l1, int l2, bool ket, const double* 
         }
       }
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) P[(acc_row<false>(jj, g) * kHNc + b) * 16 + n] = acc[jj];
+      for (int jj = 0; jj < 4; ++jj) {
+        const int m1 = acc_row<false>(jj, g);
+        if (m1 < s1) P[(m1 * n2c + b) * 16 + n] = acc[jj];
+      }
     }
     __syncthreads();
     // H[m1 s2 + m2][k] = sum_b C_2[m2][b] P[m1][b][k]
@@ -115,7 +120,7 @@ __device__ __forceinline__ void build_h(int l1, int l2, bool ket, const double* 
       d4 acc = acc_zero<false>();
 #pragma unroll
       for (int st = 0; st < kHSteps; ++st) {
-        if (st < ks2) acc = mfma16<false>(a2[st], P[(m1 * kHNc + min(4 * st + g, n2c - 1)) * 16 + n], acc);
+        if (st < ks2) acc = mfma16<false>(a2[st], P[(m1 * n2c + min(4 * st + g, n2c - 1)) * 16 + n], acc);
       }
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kThreads, 1) void solid_h_kernel(
   const int64_t at = iq * kmax * kmax + i * K2 + j;
   double* H = side ? hket + at * hks : hbra + at * hbs;
   build_h(side ? cp.lc : cp.la, side ? cp.ld : cp.lb, side == 1, centers + q * 12 + 6 * side, e[i], e[kmax + j], w[i],
-          w[kmax + j], stab, H, side ? cp.ncdb : cp.nrt * cp.rb, side ? cp.nq4 : cp.np4, (double*)dyn, tid);
+          w[kmax + j], stab, H, side ? cp.ncdb : cp.nrt * cp.rb, side ? cp.nq4 : cp.np4, dyn, tid);
 }
 
 // List form: one workgroup per (list entry e0 + blockIdx.x, primitive pair (i, j) =
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(kThreads, 1) void solid_hpairs_kernel(
   const int nk4 = (nherm(l1 + l2) + 3) & ~3;
   const int nunits = solid_pair_units(l1, l2, ket);
   build_h(l1, l2, ket, (klist ? kcenters : bcenters) + ip * 6, e[i], e[kmax + j], w[i], w[kmax + j], stab,
-          h + hoff[p] + (int64_t)(i * K2 + j) * nunits * 16 * nk4, nunits, nk4, (double*)dyn, tid);
+          h + hoff[p] + (int64_t)(i * K2 + j) * nunits * 16 * nk4, nunits, nk4, dyn, tid);
 }
 
 // Persistent kernel of a solid-harmonic plan: the work loop of
@@ -276,14 +281,14 @@ hipError_t plan_solid_launch(bool pairs, dim3 grid, int lds_bytes, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t solid_hpairs_launch(int64_t nbra, int64_t nentries, int kmax, hipStream_t s, const int32_t* pl,
+hipError_t solid_hpairs_launch(int64_t nbra, int64_t nentries, int kmax, int lds, hipStream_t s, const int32_t* pl,
                                const int32_t* pn, const Shells& x, const int64_t* hoff, const double* stab,
                                double* h) {
   // entries per launch: the grid's x extent in work-items stays below 2^32
   constexpr int64_t kChunk = (int64_t)1 << 22;
   for (int64_t e0 = 0; e0 < nentries; e0 += kChunk) {
     const dim3 grid((unsigned)std::min(kChunk, nentries - e0), (unsigned)(kmax * kmax));
-    hipLaunchKernelGGL(solid_hpairs_kernel, grid, dim3(kThreads), kSolidHLds, s, e0, nbra, kmax, pl, pn, x.centers,
+    hipLaunchKernelGGL(solid_hpairs_kernel, grid, dim3(kThreads), lds, s, e0, nbra, kmax, pl, pn, x.centers,
                        x.exps, x.coefs, x.kcenters, x.kexps, x.kcoefs, hoff, stab, h);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -301,16 +306,18 @@ hipError_t solid_set_attrs() {
     if (e != hipSuccess) return e;
   }
   const hipError_t e = hipFuncSetAttribute((const void*)solid_h_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kSolidHLds);
+                                           kSolidHLdsMax);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)solid_hpairs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kSolidHLds);
+  return hipFuncSetAttribute((const void*)solid_hpairs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             kSolidHLdsMax);
 }
 
 hipError_t solid_h_launch(const ClassParams& p, int64_t nq, hipStream_t s, const double* centers, const double* exps,
                           const double* coefs, const int32_t* nprim, const double* stab, double* hbra, double* hket,
                           int64_t q0, int64_t hbs, int64_t hks) {
   const dim3 grid((unsigned)nq, (unsigned)(2 * p.kmax * p.kmax));
-  hipLaunchKernelGGL(solid_h_kernel, grid, dim3(kThreads), kSolidHLds, s, p, centers, exps, coefs, nprim, stab, hbra,
+  const int lds = std::max(solid_h_lds(p.la, p.lb, p.np4), solid_h_lds(p.lc, p.ld, p.nq4));
+  hipLaunchKernelGGL(solid_h_kernel, grid, dim3(kThreads), lds, s, p, centers, exps, coefs, nprim, stab, hbra,
                      hket, q0, hbs, hks);
   return hipGetLastError();
 }
