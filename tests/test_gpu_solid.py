@@ -222,3 +222,39 @@ def test_solid_plan_argument_errors(torch):
                                                           w.numel(), eri4._ptr(out, "float64"), None))
     with pytest.raises(eri4.Eri4Error, match="unknown|is for|arch|open"):
         eri4.SolidPlan(b.lq, b.nprim, b.kmax, tune_file="/nonexistent/tile_table.txt")
+
+
+def test_solid_plan_and_coulomb_batch_replay_in_a_hip_graph(torch):
+    """A solid quartet plan (H build plus persistent kernel) and the J-engine
+    Coulomb batch captured in one HIP graph (no allocation, no memset nodes)
+    give the eager results on every replay, with eager work in between."""
+    b = inputs.uneven_batch(nq=10, seed=467, lvals=(3, 4, 5), kmax=2)
+    p = eri4.SolidPlan(b.lq, b.nprim, b.kmax, tune_file=eri4.TUNE_FILE)
+    C, E, Co = dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs)
+    work = torch.empty(max(1, p.work_size), dtype=torch.float64, device="cuda")
+    eager_s = p.execute(C, E, Co, work=work).clone()
+    ls = (5, 4, 4, 5)
+    c = inputs.class_batch(ls, 4, 2, seed=468, exp_range=(0.05, 200.0))
+    D = dev(torch, inputs.ket_densities(c, seed=469))
+    cC, cE, cCo, cN = dev(torch, c.centers), dev(torch, c.exps), dev(torch, c.coefs), dev(torch, c.nprim)
+    cwork = torch.empty(eri4.coulomb_work_size(ls, 2, 4), dtype=torch.float64, device="cuda")
+    eager_c = eri4.batch_coulomb(ls, cC, cE, cCo, cN, D, work=cwork).clone()
+    torch.cuda.synchronize()
+    out_s = torch.zeros_like(eager_s)
+    out_c = torch.zeros_like(eager_c)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        p.execute(C, E, Co, out=out_s, work=work, stream=s)
+        eri4.batch_coulomb(ls, cC, cE, cCo, cN, D, work=cwork, out=out_c, stream=s)
+    for rep in range(3):
+        out_s.zero_()
+        out_c.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_s, eager_s), rep
+        assert torch.equal(out_c, eager_c), rep
+        eri4.batch(ls, cC[:1].contiguous(), cE[:1].contiguous(), cCo[:1].contiguous(), cN[:1].contiguous())
+        torch.cuda.synchronize()
