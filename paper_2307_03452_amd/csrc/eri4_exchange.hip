@@ -15,64 +15,89 @@ namespace {
 // centres c[0..5], for every row b < nb of the density block D[Nb][Nd] (device
 // memory), in the operand order of exch_gemm: F^b at out + b * fbs, with
 // out[(cc * nq4 / 4 + s) * 64 + l] = F^b[4 s + l / 16][16 cc + l % 16], zero
-// past the nq Hermite functions and the nc components.  Each thread forms the
-// nd products E_cd^q of one (q, c) once and contracts them with every row of
-// D.  Called by all threads of a workgroup.
+// past the nq Hermite functions and the nc components.  On the FP64 matrix
+// cores: for each Hermite index q and block of 16 components c, the nb x 16
+// block F[b][q][c] = sum_d D[b][d] E_cd^q is one product over d (A: D held in
+// registers, B: E_cd^q formed from the three 1-d tables).  Called by all
+// threads of a workgroup.
 __device__ __forceinline__ void build_f(int lc, int ld, int nb, const double* __restrict__ c, double z1, double z2,
                                         double w1, double w2, const double* __restrict__ D,
                                         double* __restrict__ out, int64_t fbs, int tid) {
   constexpr int kNd = ncart(kTableLMax);
+  constexpr int kSd = (kNd + 3) / 4;   // MFMA k steps over d, at most
+  constexpr int kCb = (kNd + 15) / 16;  // 16-wide blocks of b, at most
   __shared__ double tabs[kMaxEtab];
   __shared__ double pair[16];
   __shared__ int2 qt[kMaxHerm + 16];
-  __shared__ int3 cdx[kNd * kNd];  // E-table rows of each (c, d)
-  const int lane = tid & 63;
+  __shared__ int cart[2][kNd];  // (x, y, z) of each component of shells c and d, packed
+  const int lane = tid & 63, g = lane >> 4, n = lane & 15, wave = tid >> 6;
   const int Lk = lc + ld, nq = nherm(Lk), nq4 = (nq + 3) & ~3;
   const int tkrow = odd_row(Lk + 2), tkaxis = ((lc + 1) * (ld + 1) + 1) * tkrow;
   const int nc = ncart(lc), nd = ncart(ld), ncc = (nc + 15) / 16;
+  const int ksd = (nd + 3) >> 2, ncb = (nb + 15) >> 4;
   if (tid == 0) make_pair(pair, z1, z2, w1, w2, c, c + 3);
   build_htab(qt, Lk, nq, nq4, 0, 0, false, tid);
-  for (int cd = tid; cd < nc * nd; cd += kThreads) {
-    const int ic = cd / nd, id = cd - (cd / nd) * nd;
-    int cx, cy, cz, dx, dy, dz;
-    cart_of(lc, ic, cx, cy, cz);
-    cart_of(ld, id, dx, dy, dz);
-    cdx[cd] = make_int3((cx * (ld + 1) + dx) * tkrow, tkaxis + (cy * (ld + 1) + dy) * tkrow,
-                        2 * tkaxis + (cz * (ld + 1) + dz) * tkrow);
+  for (int e = tid; e < 2 * kNd; e += kThreads) {
+    const int sh = e / kNd, k = e - sh * kNd, l = sh ? ld : lc;
+    int x = 0, y = 0, z = 0;
+    if (k < ncart(l)) cart_of(l, k, x, y, z);
+    cart[sh][k] = x | (y << 8) | (z << 16);
   }
   __syncthreads();
   if (tid < 64) build_etab(tabs, lc, ld, tkrow, tkaxis, 0.5 / pair[0], pair + 5, pair + 8, true, lane);
-  __syncthreads();
-  const int total = ncc * nq4 * 16;
-  for (int e = tid; e < total; e += kThreads) {
-    const int blk = e >> 6, l = e & 63;
-    const int cc = blk / (nq4 / 4), st = blk - cc * (nq4 / 4);
-    const int kq = 4 * st + (l >> 4), ic = 16 * cc + (l & 15);
-    const bool valid = kq < nq && ic < nc;
-    double ev[kNd];
-    if (valid) {
-      const int hx = qt[kq].x;
-      const int t = hx & 0xff, u = (hx >> 8) & 0xff, w = (hx >> 16) & 0xff;
-      const int3* row = cdx + ic * nd;
+  // A operands: lane (n, g) holds D[16 cb + n][4 s + g] (zero past nb, nd), and
+  // the table row offsets of component d = 4 s + g of shell d
+  double bd[kCb][kSd];
+  int rdx[kSd], rdy[kSd], rdz[kSd];
 #pragma unroll
-      for (int id = 0; id < kNd; ++id) {
-        if (id < nd) {
-          const int3 o = row[id];
-          ev[id] = tabs[o.x + t] * tabs[o.y + u] * tabs[o.z + w];
-        } else {
-          ev[id] = 0.0;
-        }
+  for (int st = 0; st < kSd; ++st) {
+    const int d = 4 * st + g;
+    const int cd = cart[1][min(d, nd - 1)];
+    rdx[st] = cd & 0xff;
+    rdy[st] = (cd >> 8) & 0xff;
+    rdz[st] = (cd >> 16) & 0xff;
+#pragma unroll
+    for (int cb = 0; cb < kCb; ++cb) {
+      const int b = 16 * cb + n;
+      bd[cb][st] = (b < nb && d < nd) ? D[b * nd + d] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int unit = wave; unit < nq4 * ncc; unit += kWaves) {
+    const int q = unit / ncc, cc = unit - (unit / ncc) * ncc;
+    const int ci = 16 * cc + n;  // this lane's row: component c of shell c
+    const int cw = cart[0][min(ci, nc - 1)];
+    const int cx = cw & 0xff, cy = (cw >> 8) & 0xff, cz = (cw >> 16) & 0xff;
+    const int hx = qt[q].x;
+    const int t = hx & 0xff, u = (hx >> 8) & 0xff, w = (hx >> 16) & 0xff;
+    d4 acc[kCb];
+#pragma unroll
+    for (int cb = 0; cb < kCb; ++cb) acc[cb] = acc_zero<false>();
+#pragma unroll
+    for (int st = 0; st < kSd; ++st) {
+      if (st < ksd) {
+        const bool ok = ci < nc && 4 * st + g < nd;
+        const double e = ok ? tabs[(cx * (ld + 1) + rdx[st]) * tkrow + t] *
+                                  tabs[tkaxis + (cy * (ld + 1) + rdy[st]) * tkrow + u] *
+                                  tabs[2 * tkaxis + (cz * (ld + 1) + rdz[st]) * tkrow + w]
+                            : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < kCb; ++cb)
+          if (cb < ncb) acc[cb] = mfma16<false>(bd[cb][st], e, acc[cb]);
       }
     }
-    for (int b = 0; b < nb; ++b) {
-      double v = 0.0;
-      if (valid) {
-        const double* Db = D + b * nd;
+    // acc[cb]: rows b = 16 cb + acc_row, columns c = 16 cc + n, so that each
+    // store covers 16 consecutive components of four b
+    const int64_t base = (int64_t)(cc * (nq4 >> 2) + (q >> 2)) * 64 + (q & 3) * 16 + n;
 #pragma unroll
-        for (int id = 0; id < kNd; ++id)
-          if (id < nd) v += ev[id] * Db[id];
+    for (int cb = 0; cb < kCb; ++cb) {
+      if (cb < ncb) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int b = 16 * cb + acc_row<false>(jj, g);
+          if (b < nb) out[b * fbs + base] = acc[cb][jj];
+        }
       }
-      out[b * fbs + e] = v;
     }
   }
 }
