@@ -27,6 +27,8 @@ hipError_t fused_launch(const ClassParams& p, dim3 grid, hipStream_t s, const Ta
 hipError_t small_set_attrs();
 hipError_t small_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
                         const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0);
+hipError_t small4_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
+                         const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0);
 
 // Solid-harmonic output (eri4_solid.hip): the H matrices of quartets q0..q0+nq-1
 // into hbra / hket (hbs / hks doubles per primitive pair, kmax^2 pair slots

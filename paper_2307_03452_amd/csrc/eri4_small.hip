@@ -212,6 +212,210 @@ __global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(E
   }
 }
 
+// The same quartet on four waves (256 threads): the recursion over 256
+// threads, the first transform's column blocks dealt to the waves (block c to
+// wave c % 4, NCW at most per wave), the second transform's output column
+// blocks likewise.  Four waves share one quartet's LDS, so a compute unit
+// holds more waves for the same LDS, which is what bounds how many quartets
+// the one-wave kernel keeps in flight; capped at four waves per SIMD (128
+// registers, some spilled), which measured faster than three or five.
+constexpr int kSmall4Threads = 256;
+constexpr int kSmall4RE = (nherm(4 * kSmallLMax) + kSmall4Threads - 1) / kSmall4Threads;
+
+__device__ void hermite_r_4w(double* R, const double* baseM, int L, const double* PQ,
+                             const uint2 (&ent)[kSmall4RE], int tid) {
+  if (tid == 0) R[0] = baseM[L];
+  __syncthreads();
+  const double px = PQ[0], py = PQ[1], pz = PQ[2];
+  for (int m = L - 1; m >= 0; --m) {
+    const int nact = nherm(L - m);
+    double nv[kSmall4RE];
+#pragma unroll
+    for (int k = 0; k < kSmall4RE; ++k) {
+      const int e = tid + k * kSmall4Threads;
+      if (e < nact) {
+        const int o1 = (int)(ent[k].x >> 16);
+        const int o2 = (int)(ent[k].y & 0xffffu);
+        const int dir = (int)((ent[k].y >> 16) & 3u);
+        const int ri = (int)(ent[k].y >> 18);
+        const double c1 = dir == 0 ? px : (dir == 1 ? py : pz);
+        nv[k] = c1 * R[o1] + (double)max(ri - 1, 0) * R[o2];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSmall4RE; ++k) {
+      const int e = tid + k * kSmall4Threads;
+      if (e < nact && e > 0) R[ent[k].x & 0xffffu] = nv[k];
+    }
+    if (tid == 0) R[0] = baseM[m];
+    __syncthreads();
+  }
+}
+
+// One quartet (q0 + blockIdx.x) per 256-thread workgroup; RG as in
+// eri4_small_kernel, NCW: first-transform column blocks per wave (at most).
+template <int RG, int NCW>
+__global__ __launch_bounds__(kSmall4Threads) __attribute__((amdgpu_waves_per_eu(4))) void eri4_small4_kernel(
+    const ClassParams cp, const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
+    const double* __restrict__ centers, const double* __restrict__ exps, const double* __restrict__ coefs,
+    const int32_t* __restrict__ nprim, double* __restrict__ out, int64_t q0) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t q = q0 + blockIdx.x;
+  const int kmax = cp.kmax;
+  double* sh = (double*)(lds + cp.o_shell);
+  double* baseM = (double*)(lds + cp.o_base);
+  double* kpair = baseM + 32;
+  double* bpair = kpair + 16;
+  double* pqv = bpair + 16;
+  int2* ptab = (int2*)(lds + cp.o_ptab);
+  int2* qtab = (int2*)(lds + cp.o_qtab);
+  double* R = (double*)(lds + cp.o_union);
+  double* brae = (double*)(lds + cp.o_brae);
+  double* X = (double*)(lds + cp.o_union);
+  double* kete = (double*)(lds + cp.o_kete);
+  int* shn = (int*)(sh + 12 + 8 * kmax);
+  double* outq = out + q * (int64_t)cp.nab * cp.ncd;
+
+  for (int i = tid; i < 12 + 8 * kmax; i += kSmall4Threads) {
+    const int j = i - 12;
+    sh[i] = i < 12 ? centers[q * 12 + i] : (j < 4 * kmax ? exps[q * 4 * kmax + j] : coefs[q * 4 * kmax + (j - 4 * kmax)]);
+  }
+  if (tid < 4) shn[tid] = nprim[q * 4 + tid];
+  build_htab<kSmall4Threads>(ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, false, tid);
+  build_htab<kSmall4Threads>(qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, false, tid);
+  uint2 ent[kSmall4RE];
+  {
+    const uint2* rt = rtab + cp.rtab_off;
+    const int n = nherm(cp.L);
+#pragma unroll
+    for (int k = 0; k < kSmall4RE; ++k) {
+      const int e = tid + k * kSmall4Threads;
+      ent[k] = e < n ? rt[e] : make_uint2(0u, 0u);
+    }
+  }
+  __syncthreads();
+  const int Ka = shn[0], Kb = shn[1], Kc = shn[2], Kd = shn[3];
+  if (Ka < 1 || Ka > kmax || Kb < 1 || Kb > kmax || Kc < 1 || Kc > kmax || Kd < 1 || Kd > kmax) {
+    for (int i = tid; i < cp.nab * cp.ncd; i += kSmall4Threads) outq[i] = __builtin_nan("");
+    return;
+  }
+  const double* A = sh;
+  const double* B = sh + 3;
+  const double* C = sh + 6;
+  const double* D = sh + 9;
+  const double* ex = sh + 12;
+  const double* co = sh + 12 + 4 * kmax;
+  const double pref = 2.0 * pow(M_PI, 2.5);
+  // this wave's [ab|q] column blocks wave, wave + 4, ... (B operand of the first transform)
+  const int nc1 = wave < cp.nqb ? (cp.nqb - wave + 3) / 4 : 0;
+  int offq[NCW], tq[NCW];
+#pragma unroll
+  for (int c = 0; c < NCW; ++c) {
+    const int cb = min(wave + 4 * c, cp.nqb - 1);
+    offq[c] = qtab[cb * 16 + (lane & 15)].y;
+    tq[c] = 0;
+  }
+
+  for (int row0 = 0; row0 < cp.nab; row0 += RG * 16) {
+    int rowx[RG], rowy[RG], rowz[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      const int ab = row0 + r * 16 + (lane & 15);
+      if (ab < cp.nab) {
+        const int ia = ab / cp.nb, ib = ab - ia * cp.nb;
+        int ax, ay, az, bx, by, bz;
+        cart_of(cp.la, ia, ax, ay, az);
+        cart_of(cp.lb, ib, bx, by, bz);
+        rowx[r] = (ax * (cp.lb + 1) + bx) * cp.tbrow;
+        rowy[r] = cp.tbaxis + (ay * (cp.lb + 1) + by) * cp.tbrow;
+        rowz[r] = 2 * cp.tbaxis + (az * (cp.lb + 1) + bz) * cp.tbrow;
+      } else {
+        const int zr = (cp.la + 1) * (cp.lb + 1) * cp.tbrow;
+        rowx[r] = zr;
+        rowy[r] = cp.tbaxis + zr;
+        rowz[r] = 2 * cp.tbaxis + zr;
+      }
+    }
+    for (int kl = 0; kl < Kc * Kd; ++kl) {
+      if (tid == 0) {
+        const int k = kl / Kd, l = kl - (kl / Kd) * Kd;
+        make_pair(kpair, ex[2 * kmax + k], ex[3 * kmax + l], co[2 * kmax + k], co[3 * kmax + l], C, D);
+      }
+      // accumulators of this wave's NCW column blocks (acc1), or of its single
+      // block when it has one and NCW = 2 (acc1s)
+      d4 acc1[RG][NCW], acc1s[RG][1];
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        acc1s[r][0] = acc_zero<false>();
+#pragma unroll
+        for (int c = 0; c < NCW; ++c) acc1[r][c] = acc_zero<false>();
+      }
+      for (int ij = 0; ij < Ka * Kb; ++ij) {
+        if (tid == 64) {
+          const int i = ij / Kb, j = ij - (ij / Kb) * Kb;
+          make_pair(bpair, ex[i], ex[kmax + j], co[i], co[kmax + j], A, B);
+        }
+        __syncthreads();
+        if (wave == 0) {
+          if (lane < 3) pqv[lane] = bpair[2 + lane] - kpair[2 + lane];
+          if (lane <= cp.L) {
+            const double zp = bpair[0], zq = kpair[0];
+            const double zs = zp + zq;
+            const double rho = zp * zq / zs;
+            double r2 = 0.0;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+              const double dd = bpair[2 + x] - kpair[2 + x];
+              r2 += dd * dd;
+            }
+            const double F = boys_fm(lane, rho * r2, boys_tab);
+            double pw = 1.0;
+            for (int mm = 0; mm < lane; ++mm) pw *= -2.0 * rho;
+            baseM[lane] = pw * (pref / (zp * zq * sqrt(zs))) * (bpair[1] * kpair[1]) * F;
+          }
+        } else if (wave == 1) {
+          build_etab<2 * kSmallLMax + 2>(brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / bpair[0], bpair + 5,
+                                         bpair + 8, false, lane);
+        }
+        __syncthreads();
+        hermite_r_4w(R, baseM, cp.L, pqv, ent, tid);
+        if (nc1 == NCW) {
+          gemm1_range<RG, NCW, false, false>(acc1, brae, R, ptab, rowx, rowy, rowz, offq, tq, 0, cp.np4, cp.L, cp.S1,
+                                             lane);
+        } else if (NCW == 2 && nc1 == 1) {
+          const int offq1[1] = {offq[0]}, tq1[1] = {0};
+          gemm1_range<RG, 1, false, false>(acc1s, brae, R, ptab, rowx, rowy, rowz, offq1, tq1, 0, cp.np4, cp.L, cp.S1,
+                                           lane);
+        }
+        __syncthreads();
+      }
+      // [ab|q] of this wave's blocks -> LDS (over the R box), ket tables
+#pragma unroll
+      for (int r = 0; r < RG; ++r)
+#pragma unroll
+        for (int c = 0; c < NCW; ++c)
+          if (c < nc1) {
+            const int cb = wave + 4 * c;
+            const d4 v = nc1 == NCW ? acc1[r][c] : acc1s[r][0];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+              X[(r * 16 + acc_row<false>(jj, lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = v[jj];
+          }
+      if (wave == 2)
+        build_etab<2 * kSmallLMax + 2>(kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / kpair[0], kpair + 5, kpair + 8,
+                                       true, lane);
+      __syncthreads();
+      // second transform: output column blocks wave, wave + 4, ...
+      for (int cb0 = wave; cb0 < cp.ncdb; cb0 += 4)
+        gemm2_group<RG, 1, false, 4>(cp, X, kete, qtab, cb0, row0, outq, kl == 0, 1.0, lane);
+      __syncthreads();
+    }
+  }
+}
+
 template <int RG, int NCQ>
 hipError_t small_launch_t(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
                           const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0) {
@@ -233,6 +437,14 @@ hipError_t small_launch_rg(const ClassParams& p, int64_t nq, hipStream_t s, cons
   }
 }
 
+template <int RG, int NCW>
+hipError_t small4_launch_t(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
+                           const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0) {
+  hipLaunchKernelGGL((eri4_small4_kernel<RG, NCW>), dim3((unsigned)nq), dim3(kSmall4Threads), p.lds_bytes, s, p,
+                     t.boys, t.rtab, centers, exps, coefs, nprim, out, q0);
+  return hipGetLastError();
+}
+
 template <int RG, int NCQ>
 hipError_t small_attr_t() {
   return hipFuncSetAttribute((const void*)eri4_small_kernel<RG, NCQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -252,7 +464,25 @@ hipError_t small_set_attrs() {
   if (e == hipSuccess) e = small_attr_t<RG, 6>();
   A(1) A(2) A(3)
 #undef A
+  const void* k4[6] = {(const void*)eri4_small4_kernel<1, 1>, (const void*)eri4_small4_kernel<1, 2>,
+                       (const void*)eri4_small4_kernel<2, 1>, (const void*)eri4_small4_kernel<2, 2>,
+                       (const void*)eri4_small4_kernel<3, 1>, (const void*)eri4_small4_kernel<3, 2>};
+  for (const void* f : k4)
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLdsMax);
   return e;
+}
+
+hipError_t small4_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
+                         const double* exps, const double* coefs, const int32_t* nprim, double* out, int64_t q0) {
+  const bool two = p.nqb > 4;
+#define L(RG) (two ? small4_launch_t<RG, 2>(p, nq, s, t, centers, exps, coefs, nprim, out, q0) \
+                   : small4_launch_t<RG, 1>(p, nq, s, t, centers, exps, coefs, nprim, out, q0))
+  switch (p.rb) {
+    case 3: return L(3);
+    case 2: return L(2);
+    default: return L(1);
+  }
+#undef L
 }
 
 hipError_t small_launch(const ClassParams& p, int64_t nq, hipStream_t s, const Tables& t, const double* centers,
