@@ -258,3 +258,28 @@ def test_solid_plan_and_coulomb_batch_replay_in_a_hip_graph(torch):
         assert torch.equal(out_c, eager_c), rep
         eri4.batch(ls, cC[:1].contiguous(), cE[:1].contiguous(), cCo[:1].contiguous(), cN[:1].contiguous())
         torch.cuda.synchronize()
+
+
+def test_solid_plan_on_a_stream_sample_against_oracle(torch):
+    """The quartet plan over solid harmonics with the tuned tile table on 48
+    quartets of the l = 4..7, K = 3 stream batch (the benchmark's solid plan
+    leg): every quartet of classes with total l <= 18 against the oracle, and
+    the rest against the oracle's transform of the library's own Cartesian
+    integrals from the Cartesian plan (checked against the oracle elsewhere)."""
+    b = inputs.stream_batch(48, 1006)
+    p = eri4.SolidPlan(b.lq, b.nprim, b.kmax, tune_file=eri4.TUNE_FILE)
+    blocks = plan_blocks(torch, b, plan=p)
+    cp = eri4.Plan(b.lq, b.nprim, b.kmax, tune_file=eri4.TUNE_FILE)
+    cart = cp.execute(dev(torch, b.centers), dev(torch, b.exps), dev(torch, b.coefs))
+    torch.cuda.synchronize()
+    cart = cart.cpu().numpy()
+    coff = cp.offsets()
+    small = [q for q in range(b.nq) if int(b.lq[q].sum()) <= 18]
+    assert small, "sample has no small classes"
+    sub = inputs.subset(b, small)
+    check_plan(torch, sub, [blocks[q] for q in small])
+    for q in range(b.nq):
+        ls = tuple(int(x) for x in b.lq[q])
+        n = [(l + 1) * (l + 2) // 2 for l in ls]
+        c = cart[coff[q]:coff[q] + int(np.prod(n))].reshape([1] + n)
+        check(blocks[q][None], solid.cart_to_solid(c, ls), c, ls)
