@@ -708,8 +708,8 @@ def main():
         args.secondary_steps = args.uneven_steps = args.mixed_steps = args.stream_steps = args.solid_steps = 0
         args.no_cpu_baseline = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (quartets shard across GPUs "
-              "with no communication; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (quartets would shard across GPUs "
+              "with no communication). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     from paper_2307_03452_amd import metrics

@@ -88,8 +88,8 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_03452_amd.build` "
-                               "(or __graft_entry__.build()); there is no non-HIP fallback")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_03452_amd.build`; "
+                               "there is no non-HIP fallback")
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         L.eri4_ncart.argtypes = [c_int]
