@@ -220,8 +220,10 @@ eri4_status ensure_device(DeviceState** st) {
 
 int align16(int x) { return (x + 15) & ~15; }
 
-// Class parameters and LDS layout for a tile of rb*16 bra rows.
-ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool slab, bool box2) {
+// Class parameters and LDS layout for a tile of rb*16 bra rows.  xs: row
+// stride of the [ab|q] staging area in doubles (0: 16 * nqb + 2, every column
+// the first transform's accumulators hold).
+ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool slab, bool box2, int xs = 0) {
   ClassParams p{};
   p.rb = rb;
   p.slab = slab ? 1 : 0;
@@ -238,7 +240,7 @@ ClassParams make_params(int la, int lb, int lc, int ld, int kmax, int rb, bool s
   p.tbrow = odd_row(p.Lb + 2); p.tkrow = odd_row(p.Lk + 2);
   p.tbaxis = ((la + 1) * (lb + 1) + 1) * p.tbrow;
   p.tkaxis = ((lc + 1) * (ld + 1) + 1) * p.tkrow;
-  p.xs = 16 * p.nqb + 2;
+  p.xs = xs > 0 ? xs : 16 * p.nqb + 2;
   p.kmax = kmax;
   int off = 0;
   p.o_shell = off; off = align16(off + (12 + 8 * kmax) * 8 + 4 * 4);
@@ -288,18 +290,27 @@ bool pick_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d,
   return false;
 }
 
-// The one-wave kernel's parameters for classes whose shells all have l <=
+// The low-l kernels: one wave per quartet for kets of at most four [ab|q]
+// column blocks, four waves for more.
+bool small_four_waves(const ClassParams& p) { return p.nqb > 4; }
+
+// The low-l kernels' parameters for classes whose shells all have l <=
 // kSmallLMax: box layout, rb = bra row blocks per pass (at most 3, with at
-// most 12 first-transform accumulator blocks of 16 x 16).
+// most 12 first-transform accumulator blocks of 16 x 16, spread evenly over
+// the passes: (fd|fd)'s 4 row blocks run as 2 + 2, not 3 + 1).  The [ab|q]
+// rows hold only the nq4 columns the second transform reads (the kernels
+// store no others); the one-wave kernel keeps the recursion table for L in
+// the last align16(8 nherm(L)) bytes.
 bool small_params(int la, int lb, int lc, int ld, int kmax, const DeviceState* d, ClassParams* out) {
   if (la > kSmallLMax || lb > kSmallLMax || lc > kSmallLMax || ld > kSmallLMax) return false;
   const int nrb = (ncart(la) * ncart(lb) + 15) / 16, nqb = (nherm(lc + ld) + 15) / 16;
-#ifndef ERI4_SMALL_RGMAX
-#define ERI4_SMALL_RGMAX 3
-#endif
-  int rg = std::min(nrb, ERI4_SMALL_RGMAX);
+  int rg = std::min(nrb, 3);
   while (rg > 1 && rg * nqb > 12) --rg;
-  ClassParams p = make_params(la, lb, lc, ld, kmax, rg, false, false);
+  const int passes = (nrb + rg - 1) / rg;
+  rg = (nrb + passes - 1) / passes;
+  const int nq4 = (nherm(lc + ld) + 3) & ~3;
+  ClassParams p = make_params(la, lb, lc, ld, kmax, rg, false, false, nq4 + 2);
+  if (!small_four_waves(p)) p.lds_bytes += align16(8 * nherm(p.L));
   if (p.lds_bytes > kSmallLdsMax || p.nqb > 6) return false;
   p.rtab_off = d ? d->rstart[p.L] : 0;
   *out = p;
@@ -376,9 +387,8 @@ eri4_status eri4_batch(int la, int lb, int lc, int ld, int64_t nquartets, const 
       const int64_t nq = std::min(qchunk, nquartets - q0);
       // four waves per quartet for kets with more than four [ab|q] column
       // blocks, one wave otherwise (measured: (ff|ff) 10-16% faster on four
-      // waves at K_bra K_ket = 1, 5 and 25; (dd|dd) 18% and 5% slower at 1 and
-      // 5, 10% faster at 25)
-      const bool four = p.nqb > 4;
+      // waves at K_bra K_ket = 1, 5 and 25; (dd|dd) faster on one wave)
+      const bool four = small_four_waves(p);
       const Tables tb{d->boys, d->rtab};
       const hipError_t e = four ? small4_launch(p, nq, stream, tb, centers, exponents, coeffs, nprim, out, q0)
                                 : small_launch(p, nq, stream, tb, centers, exponents, coeffs, nprim, out, q0);

@@ -20,23 +20,30 @@ constexpr int kSmallThreads = 64;
 constexpr int kSmallRE = 8;
 
 // eq. (md1) for decreasing m in the box layout, by one wave (entries
-// e = lane + 64 k of the recursion table for total order L).
+// e = lane + 64 k of the recursion table for total order L, read from the
+// copy in LDS: held in registers they cost 16 VGPRs for the whole kernel).
 __device__ void hermite_r_wave(double* R, const double* baseM, int L, const double* PQ,
-                               const uint2 (&ent)[kSmallRE], int lane) {
+                               const uint2* __restrict__ entl, int lane) {
   if (lane == 0) R[0] = baseM[L];
   __syncthreads();
   const double px = PQ[0], py = PQ[1], pz = PQ[2];
   for (int m = L - 1; m >= 0; --m) {
     const int nact = nherm(L - m);
     double nv[kSmallRE];
+    uint2 en[kSmallRE];
+#pragma unroll
+    for (int k = 0; k < kSmallRE; ++k) {
+      const int e = lane + k * kSmallThreads;
+      en[k] = e < nact ? entl[e] : make_uint2(0u, 0u);
+    }
 #pragma unroll
     for (int k = 0; k < kSmallRE; ++k) {
       const int e = lane + k * kSmallThreads;
       if (e < nact) {
-        const int o1 = (int)(ent[k].x >> 16);
-        const int o2 = (int)(ent[k].y & 0xffffu);
-        const int dir = (int)((ent[k].y >> 16) & 3u);
-        const int ri = (int)(ent[k].y >> 18);
+        const int o1 = (int)(en[k].x >> 16);
+        const int o2 = (int)(en[k].y & 0xffffu);
+        const int dir = (int)((en[k].y >> 16) & 3u);
+        const int ri = (int)(en[k].y >> 18);
         const double c1 = dir == 0 ? px : (dir == 1 ? py : pz);
         nv[k] = c1 * R[o1] + (double)max(ri - 1, 0) * R[o2];
       }
@@ -45,22 +52,23 @@ __device__ void hermite_r_wave(double* R, const double* baseM, int L, const doub
 #pragma unroll
     for (int k = 0; k < kSmallRE; ++k) {
       const int e = lane + k * kSmallThreads;
-      if (e < nact && e > 0) R[ent[k].x & 0xffffu] = nv[k];
+      if (e < nact && e > 0) R[en[k].x & 0xffffu] = nv[k];
     }
     if (lane == 0) R[0] = baseM[m];
     __syncthreads();
   }
 }
 
-// Second transform of the RG row blocks in X, in column groups of up to 4
-// output column blocks, written (kl == 0) or added to the output.
+// Second transform of the RG row blocks in X, in column groups of up to 3
+// output column blocks, written (kl == 0) or added to the output.  (Groups of
+// 4 hold 96 accumulator registers for RG = 3, which keeps the kernel from
+// running two waves per SIMD.)
 template <int RG>
 __device__ __forceinline__ void small_gemm2(const ClassParams& cp, const double* __restrict__ X,
                                             const double* __restrict__ kete, const int2* __restrict__ qtab,
                                             int row0, double* __restrict__ outq, bool first, int lane) {
-  for (int cb0 = 0; cb0 < cp.ncdb; cb0 += 4) {
-    switch (min(4, cp.ncdb - cb0)) {
-      case 4: gemm2_group<RG, 4, false, 1>(cp, X, kete, qtab, cb0, row0, outq, first, 1.0, lane); break;
+  for (int cb0 = 0; cb0 < cp.ncdb; cb0 += 3) {
+    switch (min(3, cp.ncdb - cb0)) {
       case 3: gemm2_group<RG, 3, false, 1>(cp, X, kete, qtab, cb0, row0, outq, first, 1.0, lane); break;
       case 2: gemm2_group<RG, 2, false, 1>(cp, X, kete, qtab, cb0, row0, outq, first, 1.0, lane); break;
       default: gemm2_group<RG, 1, false, 1>(cp, X, kete, qtab, cb0, row0, outq, first, 1.0, lane); break;
@@ -68,15 +76,22 @@ __device__ __forceinline__ void small_gemm2(const ClassParams& cp, const double*
   }
 }
 
+// Waves per SIMD the one-wave kernel is compiled for: two (at most 256
+// registers) wherever that costs at most a register or two of spills, one
+// (the compiler may use all 512) for 3 row blocks x 4 column blocks, whose 96
+// first-transform accumulators leave too little for the rest.  Measured on
+// 4096 quartets: two waves per SIMD made (dd|dd) 1.5-1.6x and (pp|pp) 1.8x
+// faster; (3, 4) on two waves spills 132 bytes per lane and was 11% slower.
+template <int RG, int NCQ>
+constexpr int small_waves() { return RG * NCQ >= 12 ? 1 : 2; }
+
 // One quartet (q0 + blockIdx.x) per 64-lane workgroup.  RG: bra row blocks
 // held in the first transform's accumulators at a time (the X region of cp
-// holds RG * 16 rows); NCQ: 16-wide column blocks of [ab|q] (cp.nqb).
-// Box layout of R (cp.lay == kLayBox, L <= 12).
+// holds RG * 16 rows); NCQ: 16-wide column blocks of [ab|q] (cp.nqb, at most
+// 4).  Box layout of R (cp.lay == kLayBox, L <= 12).  The last
+// align16(8 nherm(L)) bytes of the dynamic LDS hold the recursion entries.
 template <int RG, int NCQ>
-#ifndef ERI4_SMALL_WPE
-#define ERI4_SMALL_WPE 1
-#endif
-__global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(ERI4_SMALL_WPE))) void eri4_small_kernel(
+__global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(small_waves<RG, NCQ>()))) void eri4_small_kernel(
     const ClassParams cp, const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
     const double* __restrict__ centers, const double* __restrict__ exps, const double* __restrict__ coefs,
     const int32_t* __restrict__ nprim, double* __restrict__ out, int64_t q0) {
@@ -105,15 +120,10 @@ __global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(E
   if (lane < 4) shn[lane] = nprim[q * 4 + lane];
   build_htab<kSmallThreads>(ptab, cp.Lb, cp.np, cp.np4, cp.S1, cp.S2, false, lane);
   build_htab<kSmallThreads>(qtab, cp.Lk, cp.nq, 16 * cp.nqb, cp.S1, cp.S2, false, lane);
-  uint2 ent[kSmallRE];
+  uint2* entl = (uint2*)(lds + cp.lds_bytes - ((8 * nherm(cp.L) + 15) & ~15));
   {
     const uint2* rt = rtab + cp.rtab_off;
-    const int n = nherm(cp.L);
-#pragma unroll
-    for (int k = 0; k < kSmallRE; ++k) {
-      const int e = lane + k * kSmallThreads;
-      ent[k] = e < n ? rt[e] : make_uint2(0u, 0u);
-    }
+    for (int e = lane; e < nherm(cp.L); e += kSmallThreads) entl[e] = rt[e];
   }
   __syncthreads();
   const int Ka = shn[0], Kb = shn[1], Kc = shn[2], Kd = shn[3];
@@ -191,19 +201,22 @@ __global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(E
         }
         build_etab<2 * kSmallLMax + 2>(brae, cp.la, cp.lb, cp.tbrow, cp.tbaxis, 0.5 / bpair[0], bpair + 5, bpair + 8, false, lane);
         __syncthreads();
-        hermite_r_wave(R, baseM, cp.L, pqv, ent, lane);
+        hermite_r_wave(R, baseM, cp.L, pqv, entl, lane);
         gemm1_range<RG, NCQ, false, false>(acc1, brae, R, ptab, rowx, rowy, rowz, offq, tq, 0, cp.np4, cp.L, cp.S1,
                                            lane);
         __syncthreads();
       }
       // [ab|q] of the RG row blocks -> LDS (over the R box), ket tables
+      // (only the nq4 columns the second transform reads: rows are cp.xs long)
 #pragma unroll
       for (int r = 0; r < RG; ++r)
 #pragma unroll
         for (int c = 0; c < NCQ; ++c)
+          if (c * 16 + (lane & 15) < cp.nq4) {
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj)
-            X[(r * 16 + acc_row<false>(jj, lane >> 4)) * cp.xs + c * 16 + (lane & 15)] = acc1[r][c][jj];
+            for (int jj = 0; jj < 4; ++jj)
+              X[(r * 16 + acc_row<false>(jj, lane >> 4)) * cp.xs + c * 16 + (lane & 15)] = acc1[r][c][jj];
+          }
       build_etab<2 * kSmallLMax + 2>(kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / kpair[0], kpair + 5, kpair + 8, true, lane);
       __syncthreads();
       small_gemm2<RG>(cp, X, kete, qtab, row0, outq, kl == 0, lane);
@@ -392,7 +405,7 @@ __global__ __launch_bounds__(kSmall4Threads) __attribute__((amdgpu_waves_per_eu(
       for (int r = 0; r < RG; ++r)
 #pragma unroll
         for (int c = 0; c < NCW; ++c)
-          if (c < nc1) {
+          if (c < nc1 && (wave + 4 * c) * 16 + (lane & 15) < cp.nq4) {  // the nq4 columns read next
             const int cb = wave + 4 * c;
             const d4 v = acc1[r][c];
 #pragma unroll
@@ -427,8 +440,7 @@ hipError_t small_launch_rg(const ClassParams& p, int64_t nq, hipStream_t s, cons
     case 2: return small_launch_t<RG, 2>(p, nq, s, t, centers, exps, coefs, nprim, out, q0);
     case 3: return small_launch_t<RG, 3>(p, nq, s, t, centers, exps, coefs, nprim, out, q0);
     case 4: return small_launch_t<RG, 4>(p, nq, s, t, centers, exps, coefs, nprim, out, q0);
-    case 5: return small_launch_t<RG, 5>(p, nq, s, t, centers, exps, coefs, nprim, out, q0);
-    default: return small_launch_t<RG, 6>(p, nq, s, t, centers, exps, coefs, nprim, out, q0);
+    default: return hipErrorInvalidValue;  // more column blocks go to the four-wave kernel
   }
 }
 
@@ -454,9 +466,7 @@ hipError_t small_set_attrs() {
   if (e == hipSuccess) e = small_attr_t<RG, 1>();                                                                     \
   if (e == hipSuccess) e = small_attr_t<RG, 2>();                                                                     \
   if (e == hipSuccess) e = small_attr_t<RG, 3>();                                                                     \
-  if (e == hipSuccess) e = small_attr_t<RG, 4>();                                                                     \
-  if (e == hipSuccess) e = small_attr_t<RG, 5>();                                                                     \
-  if (e == hipSuccess) e = small_attr_t<RG, 6>();
+  if (e == hipSuccess) e = small_attr_t<RG, 4>();
   A(1) A(2) A(3)
 #undef A
   const void* k4[6] = {(const void*)eri4_small4_kernel<1, 1>, (const void*)eri4_small4_kernel<1, 2>,
