@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the committed profile notes.
 
-Two subcommands, both reading rocprofv3's CSV output and keeping only the
+Three subcommands, all reading rocprofv3's CSV output and keeping only the
 dispatches of one kernel (a substring of its name) launched with one grid size
 (total work-items), so that a run with several workloads cannot mix them:
 
@@ -18,6 +18,14 @@ dispatches of one kernel (a substring of its name) launched with one grid size
     dispatches, each divided by the ratio the same counter reads to the true
     bytes of a copy kernel (read copy_bytes, write copy_bytes), summed into HBM
     bytes per launch.
+
+  python -m paper_2307_03452_amd.profsum counters --csv <pass1.csv> <pass2.csv> ...
+      --kernel eri4_fused_kernel --grid 6553600 [--duration-ns 10212859] [--title ...]
+      [--command ...] [--sources ...]
+    Markdown: every counter of the passes averaged over the matching
+    dispatches, and the ratios below where their counters were collected.
+    GRBM_GUI_ACTIVE is read as GPU clock cycles summed over the XCDs
+    (--xcds); SIMD cycles are those times the SIMDs (--simds).
 """
 import argparse
 import csv
@@ -147,6 +155,64 @@ def traffic(a):
     print(text)
 
 
+def counters(a):
+    vals, nd = {}, {}
+    for path in a.csv:
+        names = sorted({r["Counter_Name"] for r in _rows(path) if _match(r, a.kernel, a.grid)})
+        for n in names:
+            v, k = _counter_mean(path, n, a.kernel, a.grid)
+            if n in vals:  # a counter collected in several passes (GRBM_GUI_ACTIVE): keep every pass's mean
+                vals[n] = (vals[n] * nd[n] + v * k) / (nd[n] + k)
+                nd[n] += k
+            else:
+                vals[n], nd[n] = v, k
+    if not vals:
+        sys.exit(f"no counters for {a.kernel} (grid {a.grid})")
+    out = [f"# rocprofv3 counters: {a.title}", ""]
+    if a.command:
+        out += ["Commands (repo root = <repo>, one MI355X; one counter pass per run):", ""]
+        out += ["    " + c for c in a.command] + [""]
+    out += [f"Kernel `{a.kernel}`, grid {a.grid} work-items; each value is the mean over the matching dispatches "
+            "of its pass.", "", "| counter | per dispatch | dispatches |", "|---|---|---|"]
+    out += [f"| {n} | {vals[n]:.4g} | {nd[n]} |" for n in sorted(vals)]
+    rows = []
+    cyc = vals.get("GRBM_GUI_ACTIVE")
+    if cyc:
+        c = cyc / a.xcds
+        line = f"| kernel cycles = GRBM_GUI_ACTIVE / {a.xcds} XCDs | {c:.4g} |"
+        if a.duration_ns:
+            line = line[:-1] + f" (at the traced {a.duration_ns / 1e6:.3f} ms: {c / a.duration_ns:.3f} GHz) |"
+        rows.append(line)
+        simd = a.simds * c
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in vals:
+            rows.append(f"| SQ_VALU_MFMA_BUSY_CYCLES / ({a.simds} SIMDs x kernel cycles) | "
+                        f"{vals['SQ_VALU_MFMA_BUSY_CYCLES'] / simd:.3f} |")
+        if "SQ_INSTS_MFMA" in vals:
+            rows.append(f"| SQ_INSTS_MFMA x {a.mfma_cycles} cycles / ({a.simds} SIMDs x kernel cycles) | "
+                        f"{vals['SQ_INSTS_MFMA'] * a.mfma_cycles / simd:.3f} |")
+    for num, den, what in (("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "waves waiting on any dependency"),
+                           ("SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES", "waves waiting on LDS"),
+                           ("SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "waves waiting (any reason)"),
+                           ("SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS", "LDS bank-conflict cycles per LDS-active "
+                                                                          "cycle"),
+                           ("SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ busy per GPU-active cycle")):
+        if num in vals and den in vals and vals[den]:
+            rows.append(f"| {num} / {den} ({what}) | {vals[num] / vals[den]:.3f} |")
+    if rows:
+        out += ["", "| ratio | value |", "|---|---|"] + rows
+    if a.flops and a.duration_ns:
+        tf = a.flops / (a.duration_ns * 1e-9) / 1e12
+        out += ["", f"MD4 matrix FLOPs per launch {a.flops:.5g} over the traced {a.duration_ns / 1e6:.3f} ms: "
+                    f"{100 * tf / FP64_PEAK_TFLOPS:.1f}% of the {FP64_PEAK_TFLOPS} TFLOP/s FP64 peak"]
+    if a.sources:
+        out += ["", f"Source hash ({', '.join(os.path.basename(s) for s in a.sources)}): {source_hash(a.sources)}"]
+    text = "\n".join(out) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -174,8 +240,21 @@ def main(argv=None):
     c.add_argument("--sources", nargs="*", default=[])
     c.add_argument("--command", nargs="*", default=[])
     c.add_argument("--out")
+    n = sub.add_parser("counters")
+    n.add_argument("--csv", nargs="+", required=True)
+    n.add_argument("--kernel", required=True)
+    n.add_argument("--grid", type=int)
+    n.add_argument("--xcds", type=int, default=8)
+    n.add_argument("--simds", type=int, default=1024)
+    n.add_argument("--mfma-cycles", type=int, default=64, help="cycles of one FP64 16x16x4 MFMA")
+    n.add_argument("--duration-ns", type=float)
+    n.add_argument("--flops", type=float)
+    n.add_argument("--title", default="")
+    n.add_argument("--command", nargs="*", default=[])
+    n.add_argument("--sources", nargs="*", default=[])
+    n.add_argument("--out")
     a = ap.parse_args(argv)
-    (trace if a.cmd == "trace" else traffic)(a)
+    {"trace": trace, "traffic": traffic, "counters": counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
