@@ -190,12 +190,12 @@ def counters(a):
         if "SQ_INSTS_MFMA" in vals:
             rows.append(f"| SQ_INSTS_MFMA x {a.mfma_cycles} cycles / ({a.simds} SIMDs x kernel cycles) | "
                         f"{vals['SQ_INSTS_MFMA'] * a.mfma_cycles / simd:.3f} |")
+        if "SQ_LDS_BANK_CONFLICT" in vals:
+            rows.append(f"| SQ_LDS_BANK_CONFLICT / ({a.simds // 4} CUs x kernel cycles) (share of LDS cycles lost "
+                        f"to bank conflicts) | {vals['SQ_LDS_BANK_CONFLICT'] / (a.simds // 4 * c):.3f} |")
     for num, den, what in (("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "waves waiting on any dependency"),
                            ("SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES", "waves waiting on LDS"),
-                           ("SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "waves waiting (any reason)"),
-                           ("SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS", "LDS bank-conflict cycles per LDS-active "
-                                                                          "cycle"),
-                           ("SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ busy per GPU-active cycle")):
+                           ("SQ_WAIT_ANY", "SQ_WAVE_CYCLES", "waves waiting (any reason)")):
         if num in vals and den in vals and vals[den]:
             rows.append(f"| {num} / {den} ({what}) | {vals[num] / vals[den]:.3f} |")
     if rows:

@@ -65,7 +65,7 @@ def test_counters_ratios(tmp_path, capsys):
         (2, k, 128, "SQ_INSTS_MFMA", 1.0), (1, "other", 64, "SQ_INSTS_MFMA", 1.0)])
     b = _write(tmp_path / "b.csv", PMC_COLS, [
         (1, k, 64, "GRBM_GUI_ACTIVE", 8.0e6), (1, k, 64, "SQ_WAIT_INST_ANY", 2.5e5),
-        (1, k, 64, "SQ_LDS_BANK_CONFLICT", 10.0), (1, k, 64, "SQ_ACTIVE_INST_LDS", 100.0)])
+        (1, k, 64, "SQ_LDS_BANK_CONFLICT", 2.56e7), (1, k, 64, "SQ_ACTIVE_INST_LDS", 100.0)])
     out = tmp_path / "c.md"
     profsum.main(["counters", "--csv", a, b, "--kernel", "eri4_fused_kernel", "--grid", "64", "--duration-ns",
                   "1e6", "--out", str(out)])
@@ -74,6 +74,6 @@ def test_counters_ratios(tmp_path, capsys):
     assert "| SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x kernel cycles) | 0.500 |" in text
     assert "| SQ_INSTS_MFMA x 64 cycles / (1024 SIMDs x kernel cycles) | 0.500 |" in text
     assert "(waves waiting on any dependency) | 0.250 |" in text
-    assert "(LDS bank-conflict cycles per LDS-active cycle) | 0.100 |" in text
+    assert "| SQ_LDS_BANK_CONFLICT / (256 CUs x kernel cycles) (share of LDS cycles lost to bank conflicts) | 0.100 |" in text
     assert "1.000 GHz" in text
     assert "| GRBM_GUI_ACTIVE | 8e+06 | 2 |" in text  # one dispatch from each pass
