@@ -268,6 +268,14 @@ __device__ void hermite_r_4w(double* R, const double* baseM, int L, const double
 
 // One quartet (q0 + blockIdx.x) per 256-thread workgroup; RG as in
 // eri4_small_kernel, NCW: first-transform column blocks per wave (at most).
+// With RG = 2 and six [ab|q] column blocks ((ff)-type kets), the first
+// transform's 2 x 6 blocks are split evenly instead: wave w takes row block
+// w / 2 and column blocks 3 (w % 2) .. 3 (w % 2) + 2, three MFMAs per k step
+// where two row blocks x two column blocks (one of them a repeat on waves 2
+// and 3) took four.
+#ifndef ERI4_SMALL4_SPLIT
+#define ERI4_SMALL4_SPLIT 1
+#endif
 template <int RG, int NCW>
 __global__ __launch_bounds__(kSmall4Threads) __attribute__((amdgpu_waves_per_eu(4))) void eri4_small4_kernel(
     const ClassParams cp, const double* __restrict__ boys_tab, const uint2* __restrict__ rtab,
@@ -323,20 +331,25 @@ __global__ __launch_bounds__(kSmall4Threads) __attribute__((amdgpu_waves_per_eu(
   const double* co = sh + 12 + 4 * kmax;
   const double pref = 2.0 * pow(M_PI, 2.5);
   // this wave's [ab|q] column blocks wave, wave + 4, ... (B operand of the first transform)
-  const int nc1 = wave < cp.nqb ? (cp.nqb - wave + 3) / 4 : 0;
-  int offq[NCW], tq[NCW];
+  constexpr bool SPLIT = ERI4_SMALL4_SPLIT && RG == 2 && NCW == 2;
+  constexpr int NR1 = SPLIT ? 1 : RG;    // first-transform row blocks of this wave
+  constexpr int NC1 = SPLIT ? 3 : NCW;   // and column blocks
+  const int rw = SPLIT ? wave >> 1 : 0;  // its row block (SPLIT)
+  // column block c of this wave, and whether it is one (not a repeat)
+  auto col_block = [&](int c) { return SPLIT ? 3 * (wave & 1) + c : wave + 4 * c; };
+  int offq[NC1], tq[NC1];
 #pragma unroll
-  for (int c = 0; c < NCW; ++c) {
-    const int cb = min(wave + 4 * c, cp.nqb - 1);
+  for (int c = 0; c < NC1; ++c) {
+    const int cb = min(col_block(c), cp.nqb - 1);
     offq[c] = qtab[cb * 16 + (lane & 15)].y;
     tq[c] = 0;
   }
 
   for (int row0 = 0; row0 < cp.nab; row0 += RG * 16) {
-    int rowx[RG], rowy[RG], rowz[RG];
+    int rowx[NR1], rowy[NR1], rowz[NR1];
 #pragma unroll
-    for (int r = 0; r < RG; ++r) {
-      const int ab = row0 + r * 16 + (lane & 15);
+    for (int r = 0; r < NR1; ++r) {
+      const int ab = row0 + (rw + r) * 16 + (lane & 15);
       if (ab < cp.nab) {
         const int ia = ab / cp.nb, ib = ab - ia * cp.nb;
         int ax, ay, az, bx, by, bz;
@@ -360,11 +373,11 @@ __global__ __launch_bounds__(kSmall4Threads) __attribute__((amdgpu_waves_per_eu(
       // accumulators of this wave's column blocks; a wave with fewer than NCW
       // also runs a repeat of the last column block, which it does not store
       // (fewer registers than a second accumulator set: measured faster)
-      d4 acc1[RG][NCW];
+      d4 acc1[NR1][NC1];
 #pragma unroll
-      for (int r = 0; r < RG; ++r) {
+      for (int r = 0; r < NR1; ++r) {
 #pragma unroll
-        for (int c = 0; c < NCW; ++c) acc1[r][c] = acc_zero<false>();
+        for (int c = 0; c < NC1; ++c) acc1[r][c] = acc_zero<false>();
       }
       for (int ij = 0; ij < Ka * Kb; ++ij) {
         if (tid == 64) {
@@ -395,23 +408,24 @@ __global__ __launch_bounds__(kSmall4Threads) __attribute__((amdgpu_waves_per_eu(
         }
         __syncthreads();
         hermite_r_4w(R, baseM, cp.L, pqv, ent, tid);
-        if (nc1 > 0)
-          gemm1_range<RG, NCW, false, false>(acc1, brae, R, ptab, rowx, rowy, rowz, offq, tq, 0, cp.np4, cp.L, cp.S1,
-                                             lane);
+        if (col_block(0) < cp.nqb)
+          gemm1_range<NR1, NC1, false, false>(acc1, brae, R, ptab, rowx, rowy, rowz, offq, tq, 0, cp.np4, cp.L, cp.S1,
+                                              lane);
         __syncthreads();
       }
       // [ab|q] of this wave's blocks -> LDS (over the R box), ket tables
 #pragma unroll
-      for (int r = 0; r < RG; ++r)
+      for (int r = 0; r < NR1; ++r)
 #pragma unroll
-        for (int c = 0; c < NCW; ++c)
-          if (c < nc1 && (wave + 4 * c) * 16 + (lane & 15) < cp.nq4) {  // the nq4 columns read next
-            const int cb = wave + 4 * c;
+        for (int c = 0; c < NC1; ++c) {
+          const int cb = col_block(c);
+          if (cb < cp.nqb && cb * 16 + (lane & 15) < cp.nq4) {  // not a repeat; the nq4 columns read next
             const d4 v = acc1[r][c];
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
-              X[(r * 16 + acc_row<false>(jj, lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = v[jj];
+              X[((rw + r) * 16 + acc_row<false>(jj, lane >> 4)) * cp.xs + cb * 16 + (lane & 15)] = v[jj];
           }
+        }
       if (wave == 2)
         build_etab<2 * kSmallLMax + 2>(kete, cp.lc, cp.ld, cp.tkrow, cp.tkaxis, 0.5 / kpair[0], kpair + 5, kpair + 8,
                                        true, lane);
