@@ -20,7 +20,7 @@ dispatches of one kernel (a substring of its name) launched with one grid size
     bytes per launch.
 
   python -m paper_2307_03452_amd.profsum counters --csv <pass1.csv> <pass2.csv> ...
-      --kernel eri4_fused_kernel --grid 6553600 [--duration-ns 10212859] [--title ...]
+      --kernel eri4_fused_kernel --grid 6553600 [--select START:STOP] [--duration-ns 10212859] [--title ...]
       [--command ...] [--sources ...]
     Markdown: every counter of the passes averaged over the matching
     dispatches, and the ratios below where their counters were collected.
@@ -119,9 +119,12 @@ def trace(a):
     print(text)
 
 
-def _counter_mean(path, counter, kernel, grid):
+def _counter_mean(path, counter, kernel, grid, select=None):
     vals = [float(r["Counter_Value"]) for r in _rows(path)
             if r.get("Counter_Name") == counter and _match(r, kernel, grid)]
+    if select:
+        i0, i1 = (int(x) for x in select.split(":"))
+        vals = vals[i0:i1]
     if not vals:
         sys.exit(f"no {counter} for {kernel} (grid {grid}) in {path}")
     return sum(vals) / len(vals), len(vals)
@@ -160,7 +163,7 @@ def counters(a):
     for path in a.csv:
         names = sorted({r["Counter_Name"] for r in _rows(path) if _match(r, a.kernel, a.grid)})
         for n in names:
-            v, k = _counter_mean(path, n, a.kernel, a.grid)
+            v, k = _counter_mean(path, n, a.kernel, a.grid, a.select)
             if n in vals:  # a counter collected in several passes (GRBM_GUI_ACTIVE): keep every pass's mean
                 vals[n] = (vals[n] * nd[n] + v * k) / (nd[n] + k)
                 nd[n] += k
@@ -173,7 +176,8 @@ def counters(a):
         out += ["Commands (repo root = <repo>, one MI355X; one counter pass per run):", ""]
         out += ["    " + c for c in a.command] + [""]
     out += [f"Kernel `{a.kernel}`, grid {a.grid} work-items; each value is the mean over the matching dispatches "
-            "of its pass.", "", "| counter | per dispatch | dispatches |", "|---|---|---|"]
+            "of its pass" + (f" numbered {a.select} in trace order" if a.select else "") + ".", "",
+            "| counter | per dispatch | dispatches |", "|---|---|---|"]
     out += [f"| {n} | {vals[n]:.4g} | {nd[n]} |" for n in sorted(vals)]
     rows = []
     cyc = vals.get("GRBM_GUI_ACTIVE")
@@ -248,6 +252,7 @@ def main(argv=None):
     n.add_argument("--simds", type=int, default=1024)
     n.add_argument("--mfma-cycles", type=int, default=64, help="cycles of one FP64 16x16x4 MFMA")
     n.add_argument("--duration-ns", type=float)
+    n.add_argument("--select", help="START:STOP, keep only these matching dispatches of each counter (in order)")
     n.add_argument("--flops", type=float)
     n.add_argument("--title", default="")
     n.add_argument("--command", nargs="*", default=[])

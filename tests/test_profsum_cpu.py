@@ -77,3 +77,12 @@ def test_counters_ratios(tmp_path, capsys):
     assert "| SQ_LDS_BANK_CONFLICT / (256 CUs x kernel cycles) (share of LDS cycles lost to bank conflicts) | 0.100 |" in text
     assert "1.000 GHz" in text
     assert "| GRBM_GUI_ACTIVE | 8e+06 | 2 |" in text  # one dispatch from each pass
+
+
+def test_counters_select(tmp_path, capsys):
+    k = "eri4_small_kernel<3, 3>"
+    a = _write(tmp_path / "a.csv", PMC_COLS, [(i, k, 64, "SQ_INSTS_MFMA", float(i)) for i in range(6)])
+    out = tmp_path / "c.md"
+    profsum.main(["counters", "--csv", a, "--kernel", "eri4_small_kernel", "--grid", "64", "--select", "2:5",
+                  "--out", str(out)])
+    assert "| SQ_INSTS_MFMA | 3 | 3 |" in out.read_text()  # mean of 2, 3, 4
