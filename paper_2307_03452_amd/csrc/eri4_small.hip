@@ -1,5 +1,5 @@
 // eri4_small.hip -- (ab|cd) for classes whose four shells all have l <= 3
-// ((dd|dd), (ff|ff) and the classes between), one wave per quartet.
+// ((dd|dd), (ff|ff) and the classes between), one or four waves per quartet.
 //
 // Their matrices are small (at most 100 x 84 for the first transform of
 // (ff|ff)), so the 8-wave tile of the fused kernel spends most of its time in
@@ -225,13 +225,13 @@ __global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(s
   }
 }
 
-// The same quartet on four waves (256 threads): the recursion over 256
-// threads, the first transform's column blocks dealt to the waves (block c to
-// wave c % 4, NCW at most per wave), the second transform's output column
-// blocks likewise.  Four waves share one quartet's LDS, so a compute unit
-// holds more waves for the same LDS, which is what bounds how many quartets
-// the one-wave kernel keeps in flight; capped at four waves per SIMD (128
-// registers, some spilled), which measured faster than three or five.
+// The same quartet on four waves (256 threads), for kets of more than four
+// [ab|q] column blocks, whose one-wave form needs more than 256 registers:
+// the recursion over 256 threads, the first transform's blocks dealt to the
+// waves (column block c to wave c % 4, NCW at most per wave; or evenly over
+// rows and columns, below), the second transform's output column blocks to
+// wave c % 4.  Capped at four waves per SIMD (128 registers, some spilled),
+// which measured faster than two, three or five.
 constexpr int kSmall4Threads = 256;
 constexpr int kSmall4RE = (nherm(4 * kSmallLMax) + kSmall4Threads - 1) / kSmall4Threads;
 
